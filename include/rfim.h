@@ -1,0 +1,153 @@
+/*
+ * rfim.h -- C ABI of the MI355X (gfx950) RFI-mitigation library: iterative
+ * time-domain and frequency-domain sigma cuts on channelised beam data
+ * (RFIm, arXiv:2001.03389, Section IV).
+ *
+ * Data model
+ *   A beam is a [nchan][row_stride] array in GPU memory, time fastest; samples
+ *   [0, nsamp) of each channel row are processed, the rest of the row is never
+ *   read or written.  Element type uint8 or float32 (finite values only).
+ *   Beams are independent: no statistic ever crosses beams (Section V-B runs
+ *   many beams side by side).
+ *
+ * Steps (Section IV)
+ *   TD (time domain, Fig. 2): per channel, over the nsamp samples of the batch,
+ *     mean mu and population standard deviation sigma; a sample with
+ *     |x - mu| > k*sigma (strict, two-sided) is replaced.
+ *   FD (frequency domain, Fig. 3): per time sample, channels are grouped into
+ *     bins of bin_size consecutive channels (0 = one bin of all channels); the
+ *     bin mean is subtracted from each channel, the same k*sigma test runs on
+ *     these mean-corrected values over all channels, and the ORIGINAL value of
+ *     an outlier is replaced by its bin's replacement value.
+ *   Replacement strategy (Section IV, the strategy parameter): RFIM_REPLACE_MEAN
+ *     = the step's mean rounded to the element type (uint8: nearest integer,
+ *     ties to even; float32: nearest float32, ties to even); RFIM_REPLACE_MEDIAN
+ *     = the lower median (rank floor((n-1)/2); float32 ordered by IEEE
+ *     totalOrder).
+ *   Each step reads the data as left by the previous step; the paper iterates
+ *   the cuts (three iterations in production, Section V-B).
+ *
+ * Exactness
+ *   Sums are exact integers and k is used as the exact binary value of the
+ *   double, so flags and outputs are bit-identical to an exact evaluation of
+ *   the definitions above, independent of launch shape.
+ *
+ * Asynchrony, ownership, errors
+ *   Calls validate their arguments on the host and return synchronously with
+ *   an error code; work is then enqueued on `stream` (a hipStream_t, NULL =
+ *   the null stream) and the call returns without waiting.  The caller owns
+ *   every in/out/flags buffer and must keep them alive until the stream
+ *   reaches the work.  Calls without a plan use a library-owned workspace that
+ *   may grow (hipMalloc) on first use of a larger shape; calls with a plan
+ *   never allocate.  A device fault surfaces as RFIM_ERR_DEVICE from a later
+ *   call or from the caller's own synchronisation.
+ */
+#ifndef RFIM_H
+#define RFIM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    RFIM_OK = 0,
+    RFIM_ERR_INVALID_ARG = -1,   /* argument outside the documented domain */
+    RFIM_ERR_UNSUPPORTED = -2,   /* valid, but not handled by this build */
+    RFIM_ERR_OUT_OF_MEMORY = -3, /* workspace allocation failed */
+    RFIM_ERR_DEVICE = -4,        /* HIP runtime or device error */
+    RFIM_ERR_BUDGET = -5         /* admission refused: HBM budget exhausted */
+} rfim_status;
+
+typedef enum { RFIM_U8 = 0, RFIM_F32 = 1 } rfim_dtype;
+typedef enum { RFIM_REPLACE_MEAN = 0, RFIM_REPLACE_MEDIAN = 1 } rfim_replace;
+typedef enum { RFIM_TD = 0, RFIM_FD = 1 } rfim_domain;
+
+/* One beam.  `in` and `out` are device pointers to [nchan][row_stride]
+ * elements; out == in processes in place (the original data is then
+ * overwritten), otherwise the two must not overlap.  `flags` (device, may be
+ * NULL) is a [nchan][row_stride] uint8 array whose bit j is set where step j
+ * replaced the sample; requires nsteps <= 8.  Constraints: 1 <= nchan < 2^31,
+ * 1 <= nsamp < 2^31, row_stride >= nsamp. */
+typedef struct {
+    int32_t dtype;    /* rfim_dtype */
+    int32_t reserved; /* must be 0 */
+    int64_t nchan;
+    int64_t nsamp;
+    int64_t row_stride; /* elements between consecutive channels */
+    const void* in;
+    void* out;
+    uint8_t* flags;
+} rfim_beam;
+
+/* One step.  k must be finite and >= 0.  bin_size (FD only) must divide
+ * nchan of every beam; 0 means a single bin of all channels. */
+typedef struct {
+    int32_t domain;  /* rfim_domain */
+    int32_t replace; /* rfim_replace */
+    double k;
+    int64_t bin_size;
+} rfim_step;
+
+typedef struct rfim_plan rfim_plan; /* opaque */
+
+/* Time-domain sigma cut (Section IV, Fig. 2): one TD step with threshold k
+ * and replacement strategy r on each beam. */
+rfim_status rfim_td_sigma_cut(const rfim_beam* beams, int32_t nbeams, double k, int32_t replace,
+                              void* stream);
+
+/* Frequency-domain sigma cut (Section IV, Fig. 3): one FD step with bins of
+ * bin_size consecutive channels (0 = all channels). */
+rfim_status rfim_fd_sigma_cut(const rfim_beam* beams, int32_t nbeams, double k, int64_t bin_size,
+                              int32_t replace, void* stream);
+
+/* Runs steps[0..nsteps) in order on every beam (the iterated TD + FD
+ * mitigation of Section V).  plan may be NULL (library workspace) or a plan
+ * created for the same beam shapes and steps. */
+rfim_status rfim_pipeline_run(const rfim_beam* beams, int32_t nbeams, const rfim_step* steps,
+                              int32_t nsteps, rfim_plan* plan, void* stream);
+
+/* Creates a plan for beams of these shapes and dtypes (pointers are ignored,
+ * except that a run must pass flags exactly where the shapes did) and this
+ * step list: chooses kernel configurations (from the tuning cache
+ * at tune_cache_path if given and present, else defaults) and allocates the
+ * device workspace, so that rfim_pipeline_run with the plan never allocates.
+ * Section III: tuned configurations are saved and reused in production. */
+rfim_status rfim_plan_create(const rfim_beam* shapes, int32_t nbeams, const rfim_step* steps,
+                             int32_t nsteps, const char* tune_cache_path, rfim_plan** out);
+rfim_status rfim_plan_destroy(rfim_plan* plan);
+
+/* Per (beam, step) number of replaced samples of the most recent run with
+ * this plan, copied to host_out[nbeams * nsteps]; synchronises the plan's
+ * last stream. */
+rfim_status rfim_plan_flag_counts(const rfim_plan* plan, uint64_t* host_out);
+
+/* Kernels the library launches, for per-kernel timing. */
+typedef enum {
+    RFIM_KERNEL_TD_ROWS_U8 = 0, /* uint8 row statistics + TD decisions */
+    RFIM_KERNEL_FUSED_U8 = 1,   /* uint8 TD apply + FD steps + write-back */
+    RFIM_KERNEL_KINDS = 2
+} rfim_kernel_kind;
+
+/* Per-kernel timing of a plan (Section V-B reports execution time averaged
+ * over many runs).  enable != 0 brackets every kernel the plan launches with
+ * HIP events on the launch stream and clears the accumulated record; 0 stops
+ * timing.  rfim_plan_kernel_times waits for the plan's last run and returns,
+ * for one kernel kind, the number of timed launches and their summed duration
+ * in milliseconds. */
+rfim_status rfim_plan_set_timing(rfim_plan* plan, int32_t enable);
+rfim_status rfim_plan_kernel_times(rfim_plan* plan, int32_t kind, uint64_t* launches,
+                                   double* total_ms);
+
+/* Human-readable text for a status code (static storage). */
+const char* rfim_status_string(rfim_status s);
+
+/* Library version as "major.minor.patch" (static storage). */
+const char* rfim_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RFIM_H */

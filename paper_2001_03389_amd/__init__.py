@@ -1,0 +1,235 @@
+"""Python binding of librfim (include/rfim.h): RFI mitigation by iterated
+time- and frequency-domain sigma cuts (RFIm, arXiv:2001.03389, Section IV) on
+MI355X.
+
+Argument marshalling only: every step runs in the HIP kernels of librfim.so.
+Tensors are torch CUDA (HIP) tensors of shape [nchan][row_stride] (uint8 or
+float32, unit stride along time); ``nsamp`` <= row_stride samples per row are
+processed.  Calls are asynchronous on the given (or current) stream.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Iterable, Sequence
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "librfim.so")
+
+RFIM_OK, RFIM_ERR_INVALID_ARG, RFIM_ERR_UNSUPPORTED = 0, -1, -2
+RFIM_ERR_OUT_OF_MEMORY, RFIM_ERR_DEVICE, RFIM_ERR_BUDGET = -3, -4, -5
+RFIM_U8, RFIM_F32 = 0, 1
+RFIM_REPLACE_MEAN, RFIM_REPLACE_MEDIAN = 0, 1
+RFIM_TD, RFIM_FD = 0, 1
+RFIM_KERNEL_TD_ROWS_U8, RFIM_KERNEL_FUSED_U8 = 0, 1
+KERNEL_NAMES = {RFIM_KERNEL_TD_ROWS_U8: "k_td_rows_u8", RFIM_KERNEL_FUSED_U8: "k_fused_u8"}
+
+
+class RfimError(RuntimeError):
+    def __init__(self, status: int, what: str = ""):
+        self.status = status
+        super().__init__(f"{what}: {status_string(status)} ({status})" if what else status_string(status))
+
+
+class rfim_beam(ctypes.Structure):
+    _fields_ = [("dtype", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("nchan", ctypes.c_int64), ("nsamp", ctypes.c_int64),
+                ("row_stride", ctypes.c_int64), ("in_", ctypes.c_void_p),
+                ("out", ctypes.c_void_p), ("flags", ctypes.c_void_p)]
+
+
+class rfim_step(ctypes.Structure):
+    _fields_ = [("domain", ctypes.c_int32), ("replace", ctypes.c_int32),
+                ("k", ctypes.c_double), ("bin_size", ctypes.c_int64)]
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """The loaded librfim.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "`python -m paper_2001_03389_amd.build` (hipcc, gfx950)")
+        L = ctypes.CDLL(LIB_PATH)
+        st, i32, i64, vp, dbl = ctypes.c_int, ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p, ctypes.c_double
+        PB, PS = ctypes.POINTER(rfim_beam), ctypes.POINTER(rfim_step)
+        L.rfim_td_sigma_cut.argtypes = [PB, i32, dbl, i32, vp]
+        L.rfim_fd_sigma_cut.argtypes = [PB, i32, dbl, i64, i32, vp]
+        L.rfim_pipeline_run.argtypes = [PB, i32, PS, i32, vp, vp]
+        L.rfim_plan_create.argtypes = [PB, i32, PS, i32, ctypes.c_char_p, ctypes.POINTER(vp)]
+        L.rfim_plan_destroy.argtypes = [vp]
+        L.rfim_plan_flag_counts.argtypes = [vp, ctypes.POINTER(ctypes.c_uint64)]
+        L.rfim_plan_set_timing.argtypes = [vp, i32]
+        L.rfim_plan_kernel_times.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_uint64),
+                                             ctypes.POINTER(ctypes.c_double)]
+        for f in ("rfim_td_sigma_cut", "rfim_fd_sigma_cut", "rfim_pipeline_run", "rfim_plan_create",
+                  "rfim_plan_destroy", "rfim_plan_flag_counts", "rfim_plan_set_timing",
+                  "rfim_plan_kernel_times"):
+            getattr(L, f).restype = st
+        L.rfim_status_string.argtypes = [st]
+        L.rfim_status_string.restype = ctypes.c_char_p
+        L.rfim_version.argtypes = []
+        L.rfim_version.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def status_string(s: int) -> str:
+    return lib().rfim_status_string(int(s)).decode()
+
+
+def version() -> str:
+    return lib().rfim_version().decode()
+
+
+def _check(rc: int, what: str):
+    if rc != RFIM_OK:
+        raise RfimError(rc, what)
+
+
+# ---------------------------------------------------------------- marshalling
+def _dtype_code(t) -> int:
+    import torch
+    if t.dtype == torch.uint8:
+        return RFIM_U8
+    if t.dtype == torch.float32:
+        return RFIM_F32
+    raise TypeError(f"unsupported dtype {t.dtype} (uint8 or float32)")
+
+
+def make_beam(inp, out=None, flags=None, nsamp: int | None = None) -> rfim_beam:
+    """Describe one beam from torch tensors [nchan][row_stride] (time fastest)."""
+    if inp.dim() != 2 or inp.stride(1) != 1:
+        raise ValueError("beam tensors must be 2-D [nchan][row_stride] with unit time stride")
+    out = inp if out is None else out
+    if out.shape != inp.shape or out.stride() != inp.stride() or out.dtype != inp.dtype:
+        raise ValueError("out must match in (shape, strides, dtype)")
+    C = inp.shape[0]
+    stride = inp.stride(0) if C > 1 else inp.shape[1]
+    T = inp.shape[1] if nsamp is None else int(nsamp)
+    b = rfim_beam()
+    b.dtype = _dtype_code(inp)
+    b.reserved = 0
+    b.nchan, b.nsamp, b.row_stride = C, T, stride
+    b.in_, b.out = inp.data_ptr(), out.data_ptr()
+    if flags is not None:
+        if flags.dtype.itemsize != 1 or flags.shape != inp.shape or flags.stride() != inp.stride():
+            raise ValueError("flags must be uint8 with the beam's shape and strides")
+        b.flags = flags.data_ptr()
+    else:
+        b.flags = None
+    return b
+
+
+def _step_fields(s):
+    if isinstance(s, rfim_step):
+        return s.domain, s.replace, s.k, s.bin_size
+    if hasattr(s, "domain"):
+        dom, k, rep, binsz = s.domain, s.k, s.replace, s.bin_size
+    else:
+        dom, k, rep, binsz = s
+    d = {"td": RFIM_TD, "fd": RFIM_FD}.get(dom, dom)
+    r = {"mean": RFIM_REPLACE_MEAN, "median": RFIM_REPLACE_MEDIAN}.get(rep, rep)
+    return int(d), int(r), float(k), int(binsz) if int(d) == RFIM_FD else 0
+
+
+def make_steps(steps: Sequence) -> ctypes.Array:
+    arr = (rfim_step * max(1, len(steps)))()
+    for i, s in enumerate(steps):
+        arr[i].domain, arr[i].replace, arr[i].k, arr[i].bin_size = _step_fields(s)
+    return arr
+
+
+def _beams(inputs, outputs, flags, nsamp):
+    n = len(inputs)
+    outputs = list(outputs) if outputs is not None else [None] * n
+    flags = list(flags) if flags is not None else [None] * n
+    nsamp = list(nsamp) if isinstance(nsamp, (list, tuple)) else [nsamp] * n
+    arr = (rfim_beam * max(1, n))()
+    for i in range(n):
+        arr[i] = make_beam(inputs[i], outputs[i], flags[i], nsamp[i])
+    return arr, n
+
+
+def _stream_handle(stream):
+    if stream is None:
+        import torch
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return ctypes.c_void_p(stream)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+# ------------------------------------------------------------------ entry points
+def rfim_pipeline_run(inputs: Sequence, steps: Sequence, outputs: Sequence | None = None,
+                      flags: Sequence | None = None, nsamp=None, plan: "Plan | None" = None,
+                      stream=None) -> None:
+    """Run ``steps`` in order on every beam (rfim_pipeline_run)."""
+    arr, n = _beams(inputs, outputs, flags, nsamp)
+    st = make_steps(steps)
+    rc = lib().rfim_pipeline_run(arr, n, st, len(steps), plan.handle if plan else None,
+                                 _stream_handle(stream))
+    _check(rc, "rfim_pipeline_run")
+
+
+def rfim_td_sigma_cut(inputs: Sequence, k: float, replace="mean", outputs=None, flags=None,
+                      nsamp=None, stream=None) -> None:
+    """One time-domain sigma cut on every beam (rfim_td_sigma_cut)."""
+    arr, n = _beams(inputs, outputs, flags, nsamp)
+    r = {"mean": RFIM_REPLACE_MEAN, "median": RFIM_REPLACE_MEDIAN}.get(replace, replace)
+    _check(lib().rfim_td_sigma_cut(arr, n, float(k), int(r), _stream_handle(stream)),
+           "rfim_td_sigma_cut")
+
+
+def rfim_fd_sigma_cut(inputs: Sequence, k: float, bin_size: int = 32, replace="mean",
+                      outputs=None, flags=None, nsamp=None, stream=None) -> None:
+    """One frequency-domain sigma cut on every beam (rfim_fd_sigma_cut)."""
+    arr, n = _beams(inputs, outputs, flags, nsamp)
+    r = {"mean": RFIM_REPLACE_MEAN, "median": RFIM_REPLACE_MEDIAN}.get(replace, replace)
+    _check(lib().rfim_fd_sigma_cut(arr, n, float(k), int(bin_size), int(r), _stream_handle(stream)),
+           "rfim_fd_sigma_cut")
+
+
+class Plan:
+    """rfim_plan_create / rfim_plan_destroy / rfim_plan_flag_counts."""
+
+    def __init__(self, inputs: Sequence, steps: Sequence, outputs=None, flags=None, nsamp=None,
+                 tune_cache: str | None = None):
+        arr, n = _beams(inputs, outputs, flags, nsamp)
+        self.nbeams, self.nsteps = n, len(steps)
+        st = make_steps(steps)
+        h = ctypes.c_void_p()
+        rc = lib().rfim_plan_create(arr, n, st, len(steps),
+                                    tune_cache.encode() if tune_cache else None, ctypes.byref(h))
+        _check(rc, "rfim_plan_create")
+        self.handle = h
+
+    def flag_counts(self):
+        buf = (ctypes.c_uint64 * (self.nbeams * self.nsteps))()
+        _check(lib().rfim_plan_flag_counts(self.handle, buf), "rfim_plan_flag_counts")
+        return [[buf[b * self.nsteps + s] for s in range(self.nsteps)] for b in range(self.nbeams)]
+
+    def set_timing(self, enable: bool = True):
+        _check(lib().rfim_plan_set_timing(self.handle, 1 if enable else 0), "rfim_plan_set_timing")
+
+    def kernel_times(self, kind: int):
+        """(launches, total milliseconds) of one kernel kind since timing was enabled."""
+        n = ctypes.c_uint64()
+        ms = ctypes.c_double()
+        _check(lib().rfim_plan_kernel_times(self.handle, int(kind), ctypes.byref(n), ctypes.byref(ms)),
+               "rfim_plan_kernel_times")
+        return int(n.value), float(ms.value)
+
+    def close(self):
+        if self.handle:
+            lib().rfim_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,148 @@
+// Exact integer arithmetic for the sigma-cut decisions (device side).
+//
+// The outlier test of Section IV, |x - mu| > k*sigma with the population
+// standard deviation, is evaluated without rounding: for a row of n samples
+// with S1 = sum x and S2 = sum x^2 it reads (n*x - S1)^2 > k^2 * (n*S2 - S1^2),
+// and for a time sample's C mean-corrected channels Z_c = B*x_c - S_b (whose
+// sum is exactly zero) it reads C*Z_c^2 > k^2 * sum Z^2.  k is the exact binary
+// value of the caller's double, k = mk * 2^ek with mk odd.  FP64 is used only to
+// estimate where the cut falls; the exact test then settles the boundary.
+#pragma once
+
+#include "rfim_internal.h"
+
+namespace rfim {
+
+typedef unsigned __int128 u128;
+typedef __int128 i128;
+
+// 512-bit unsigned integer, little-endian 64-bit limbs.
+struct U512 {
+    uint64_t w[8];
+};
+
+__device__ inline U512 u512_from(u128 v) {
+    U512 r;
+#pragma unroll
+    for (int i = 0; i < 8; i++) r.w[i] = 0;
+    r.w[0] = (uint64_t)v;
+    r.w[1] = (uint64_t)(v >> 64);
+    return r;
+}
+
+// a * b for operands below 2^128 (result below 2^256 fits easily)
+__device__ inline U512 u512_mul128(u128 a, u128 b) {
+    uint64_t a0 = (uint64_t)a, a1 = (uint64_t)(a >> 64);
+    uint64_t b0 = (uint64_t)b, b1 = (uint64_t)(b >> 64);
+    u128 p00 = (u128)a0 * b0, p01 = (u128)a0 * b1, p10 = (u128)a1 * b0, p11 = (u128)a1 * b1;
+    U512 r = u512_from(0);
+    r.w[0] = (uint64_t)p00;
+    u128 mid = (p00 >> 64) + (uint64_t)p01 + (uint64_t)p10;
+    r.w[1] = (uint64_t)mid;
+    u128 hi = (mid >> 64) + (p01 >> 64) + (p10 >> 64) + (uint64_t)p11;
+    r.w[2] = (uint64_t)hi;
+    r.w[3] = (uint64_t)((hi >> 64) + (p11 >> 64));
+    return r;
+}
+
+// a * 2^s, 0 <= s < 512 (bits shifted past 2^512 are lost; callers keep
+// values far below that)
+__device__ inline U512 u512_shl(const U512& a, int s) {
+    U512 r = u512_from(0);
+    int ws = s >> 6, bs = s & 63;
+#pragma unroll
+    for (int i = 0; i < 8; i++) {
+        int src = i - ws;
+        uint64_t v = 0;
+        if (src >= 0 && src < 8) {
+            v = a.w[src] << bs;
+            if (bs && src >= 1) v |= a.w[src - 1] >> (64 - bs);
+        }
+        r.w[i] = v;
+    }
+    return r;
+}
+
+__device__ inline int u512_cmp(const U512& a, const U512& b) {
+#pragma unroll
+    for (int i = 7; i >= 0; i--)
+        if (a.w[i] != b.w[i]) return a.w[i] < b.w[i] ? -1 : 1;
+    return 0;
+}
+
+// A <= k^2 * V, exactly.  A and V below 2^128; k as described by kx.
+__device__ inline bool le_k2(u128 A, u128 V, const KExact& kx) {
+    if (kx.mode == 1) return A == 0;   // k^2 * V < 1 for every V < 2^128
+    if (kx.mode == 2) return true;     // no outlier can exist (Samuelson)
+    u128 mk2 = ((u128)kx.mk2_hi << 64) | kx.mk2_lo;
+    U512 rhs = u512_mul128(mk2, V);
+    U512 lhs = u512_from(A);
+    if (kx.ek >= 0)
+        rhs = u512_shl(rhs, 2 * kx.ek);
+    else
+        lhs = u512_shl(lhs, -2 * kx.ek);
+    return u512_cmp(lhs, rhs) <= 0;
+}
+
+// num / den rounded to nearest, ties to even (den > 0, den < 2^62)
+__device__ inline uint64_t rn_div_u64(uint64_t num, uint64_t den) {
+    uint64_t q = num / den, r = num - q * den;
+    if (2 * r > den || (2 * r == den && (q & 1))) q++;
+    return q;
+}
+
+__device__ inline int64_t floor_div(int64_t a, int64_t b) {  // b > 0
+    int64_t q = a / b;
+    if ((a % b != 0) && (a < 0)) q--;
+    return q;
+}
+
+__device__ inline int64_t ceil_div(int64_t a, int64_t b) {  // b > 0
+    int64_t q = a / b;
+    if ((a % b != 0) && (a > 0)) q++;
+    return q;
+}
+
+// uint8 TD cut of one row with n samples, S1 = sum x, S2 = sum x^2: the set of
+// byte values that are NOT outliers is the integer interval [*lo, *hi]
+// (*lo > *hi when it is empty).
+__device__ inline void td_bounds_u8(uint64_t n, uint64_t S1, uint64_t S2, const KExact& kx,
+                                    int* lo, int* hi) {
+    u128 D = (u128)n * S2 - (u128)S1 * S1;
+    // x passes on the high side when n*x - S1 <= 0 or (n*x - S1)^2 <= k^2 D
+    auto ok_hi = [&](int64_t x) -> bool {
+        i128 d = (i128)n * x - (i128)S1;
+        if (d <= 0) return true;
+        return le_k2((u128)d * (u128)d, D, kx);
+    };
+    auto ok_lo = [&](int64_t x) -> bool {
+        i128 d = (i128)S1 - (i128)n * x;
+        if (d <= 0) return true;
+        return le_k2((u128)d * (u128)d, D, kx);
+    };
+    double mu = (double)S1 / (double)n;
+    double spread = kx.mode == 0 ? kx.k * sqrt((double)D) / (double)n : (kx.mode == 2 ? 512.0 : 0.0);
+    double eh = floor(mu + spread), el = ceil(mu - spread);
+    int64_t h = eh > 256.0 ? 256 : (eh < -1.0 ? -1 : (int64_t)eh);
+    int64_t l = el > 256.0 ? 256 : (el < -1.0 ? -1 : (int64_t)el);
+    while (h < 256 && ok_hi(h + 1)) h++;
+    while (h > -1 && !ok_hi(h)) h--;
+    while (l > -1 && ok_lo(l - 1)) l--;
+    while (l < 256 && !ok_lo(l)) l++;
+    *lo = l < 0 ? 0 : (int)l;
+    *hi = h > 255 ? 255 : (int)h;
+}
+
+// FD cut of one time sample: the largest z in [0, zcap] with C*z^2 <= k^2 SZ2;
+// channel c is an outlier exactly when |Z_c| > z (Z_c is an integer, |Z_c| <= zcap).
+__device__ inline uint64_t fd_zthr(u128 SZ2, int64_t C, const KExact& kx, uint64_t zcap) {
+    auto ok = [&](uint64_t z) -> bool { return le_k2((u128)C * ((u128)z * z), SZ2, kx); };
+    double e = kx.mode == 0 ? floor(kx.k * sqrt((double)SZ2 / (double)C))
+                            : (kx.mode == 2 ? (double)zcap : 0.0);
+    uint64_t z = e >= (double)zcap ? zcap : (e < 0.0 ? 0 : (uint64_t)e);
+    while (z < zcap && ok(z + 1)) z++;
+    while (z > 0 && !ok(z)) z--;
+    return z;
+}
+
+}  // namespace rfim

@@ -1,0 +1,66 @@
+// Internal declarations shared by the host library and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/rfim.h"
+
+namespace rfim {
+
+constexpr int kMaxSteps = 16;   // steps per pipeline (flags need <= 8)
+constexpr int kBlock = 256;     // work-group size of every kernel
+
+// Threshold k as an exact binary fraction k = mk * 2^ek (mk odd).  mode:
+//  0 = exact comparison with mk^2 = (mk2_hi:mk2_lo) and ek,
+//  1 = k so small that only exact equality with the centre passes (k = 0),
+//  2 = k so large that no sample can be an outlier (Samuelson's bound:
+//      |x - mu| <= sigma * sqrt(n - 1), and n < 2^31 <= k^2).
+struct KExact {
+    uint64_t mk2_lo, mk2_hi;
+    int32_t ek;
+    int32_t mode;
+    double k;  // the double itself, for estimates only
+};
+
+struct SegStep {
+    KExact kx;
+    int32_t replace;   // rfim_replace
+    int32_t bit;       // flag bit (step index in the caller's list), -1 = none
+    int64_t bin;       // FD bin size (resolved per beam when 0: see DevBeam)
+};
+
+// One run of consecutive TD steps followed by consecutive FD steps.
+struct Segment {
+    int32_t n_td, n_fd;
+    int32_t flags_mode;  // 0 = no flags, 1 = write fresh, 2 = OR into existing
+    int32_t pad;
+    SegStep td[kMaxSteps];
+    SegStep fd[kMaxSteps];
+};
+
+// Device-side beam record of one launch.
+struct DevBeam {
+    const void* in;
+    void* out;
+    uint8_t* flags;
+    int64_t C, T, stride;
+    int64_t row0;    // first global row (TD records) of this beam
+    int64_t tile0;   // first global tile of this beam
+    int32_t Tt;      // samples per tile of the fused kernel
+    int32_t Cp;      // LDS bytes per time sample of a tile (>= C, padded)
+    int32_t cidx;    // index of the beam in the caller's list (flag counters)
+    int32_t pad;
+};
+
+// Host launchers (defined in the .hip files).  counts (nullable) receives, per
+// beam, the number of samples each step replaced: counts[beam * count_stride + bit].
+hipError_t launch_td_rows_u8(const DevBeam* d_beams, int nbeams, int64_t total_rows,
+                             const Segment& seg, uint32_t* d_rec, unsigned long long* d_counts,
+                             int count_stride, hipStream_t s);
+hipError_t launch_fused_u8(const DevBeam* d_beams, int nbeams, int64_t total_tiles,
+                           const Segment& seg, const uint32_t* d_rec, size_t lds_bytes,
+                           unsigned long long* d_counts, int count_stride, hipStream_t s);
+hipError_t launch_zero_u64(unsigned long long* p, int64_t n, hipStream_t s);
+
+}  // namespace rfim
