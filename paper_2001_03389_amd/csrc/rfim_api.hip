@@ -29,7 +29,9 @@ hipError_t launch_zero_u64(unsigned long long* p, int64_t n, hipStream_t s) {
 namespace {
 
 constexpr int kRing = 16;                 // descriptor staging slots per workspace
-constexpr size_t kLdsBudget = 53248;      // fused-kernel LDS per work-group (3 per CU)
+// fused-kernel tile LDS per work-group: 160 KB per CU shared by 3 work-groups,
+// less the kernel's static LDS (TD exception worklist and counters)
+constexpr size_t kLdsBudget = 51200;
 constexpr size_t kLdsMax = 65536;
 
 KExact make_k(double k) {
@@ -54,6 +56,8 @@ KExact make_k(double k) {
     unsigned __int128 m2 = (unsigned __int128)mk * mk;
     r.mk2_lo = (uint64_t)m2;
     r.mk2_hi = (uint64_t)(m2 >> 64);
+    r.mk2_bits = 0;
+    for (unsigned __int128 t = m2; t; t >>= 1) r.mk2_bits++;
     r.ek = ek;
     r.mode = 0;
     return r;
@@ -138,7 +142,11 @@ std::vector<Segment> segments_of(const rfim_step* steps, int32_t nsteps) {
 
 // Tile geometry of the fused kernel for one beam.
 bool tile_shape(const rfim_beam& b, bool flags, int32_t* Tt, int32_t* Cp) {
-    int64_t cp = ((b.nchan + 3) / 4) * 4 + 4;
+    if (b.nchan >= ((int64_t)1 << 24)) return false;   // worklist packs the row in 24 bits
+    // 16-byte aligned time samples (vector LDS reads), padded off a multiple
+    // of 256 bytes so the transposed stores of neighbouring lanes spread over banks
+    int64_t cp = ((b.nchan + 15) / 16) * 16;
+    if (cp % 256 == 0 || cp % 256 == 128) cp += 16;
     size_t per = (size_t)cp * (flags ? 2 : 1);
     int t = 64;
     while (t > 4 && per * t > kLdsBudget) t >>= 1;
@@ -307,6 +315,24 @@ struct LaunchPlan {
     int nsteps = 0;
 };
 
+// True when, for every uint8 beam and FD step of the run, each lane's share
+// of a bin (a whole bin, or B/(lanes per bin) when bins span several lanes) is
+// a multiple of 16 bytes; bins then start 16-byte aligned because Cp is.
+bool fd_vec_ok(const rfim_beam* beams, const LaunchPlan& lp, const Segment& seg) {
+    for (int bi : lp.u8_beams) {
+        const rfim_beam& b = beams[bi];
+        const int G = kBlock / lp.Tt[bi];
+        for (int s = 0; s < seg.n_fd; s++) {
+            const int64_t B = seg.fd[s].bin == 0 ? b.nchan : seg.fd[s].bin;
+            const int64_t nb = b.nchan / B;
+            int64_t lpb = 1;
+            if (nb < G && (G % nb) == 0 && (B % (16 * (G / nb))) == 0) lpb = G / nb;
+            if ((B / lpb) % 16 != 0) return false;
+        }
+    }
+    return true;
+}
+
 rfim_status make_launch_plan(const rfim_beam* beams, int32_t nbeams, const rfim_step* steps,
                              int32_t nsteps, bool want_counts, LaunchPlan* lp) {
     lp->segs = segments_of(steps, nsteps);
@@ -399,8 +425,9 @@ rfim_status execute(const rfim_beam* beams, int32_t nbeams, const LaunchPlan& lp
             }));
             if (st != RFIM_OK) return st;
         }
+        const bool vec = fd_vec_ok(beams, lp, seg);
         st = dev_err(ws.timed_launch(RFIM_KERNEL_FUSED_U8, stream, [&] {
-            return launch_fused_u8(d_tab, nu8, lp.u8_tiles, seg, d_rec, lp.u8_lds, d_counts, 8,
+            return launch_fused_u8(d_tab, nu8, lp.u8_tiles, seg, d_rec, lp.u8_lds, vec, d_counts, 8,
                                    stream);
         }));
         if (st != RFIM_OK) return st;

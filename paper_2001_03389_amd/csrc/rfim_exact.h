@@ -46,21 +46,20 @@ __device__ inline U512 u512_mul128(u128 a, u128 b) {
 }
 
 // a * 2^s, 0 <= s < 512 (bits shifted past 2^512 are lost; callers keep
-// values far below that)
-__device__ inline U512 u512_shl(const U512& a, int s) {
-    U512 r = u512_from(0);
-    int ws = s >> 6, bs = s & 63;
+// values far below that).  Constant limb indices only, so it stays in registers.
+__device__ inline U512 u512_shl(U512 a, int s) {
+    for (int ws = s >> 6; ws > 0; ws--) {
 #pragma unroll
-    for (int i = 0; i < 8; i++) {
-        int src = i - ws;
-        uint64_t v = 0;
-        if (src >= 0 && src < 8) {
-            v = a.w[src] << bs;
-            if (bs && src >= 1) v |= a.w[src - 1] >> (64 - bs);
-        }
-        r.w[i] = v;
+        for (int i = 7; i > 0; i--) a.w[i] = a.w[i - 1];
+        a.w[0] = 0;
     }
-    return r;
+    const int bs = s & 63;
+    if (bs) {
+#pragma unroll
+        for (int i = 7; i > 0; i--) a.w[i] = (a.w[i] << bs) | (a.w[i - 1] >> (64 - bs));
+        a.w[0] <<= bs;
+    }
+    return a;
 }
 
 __device__ inline int u512_cmp(const U512& a, const U512& b) {
@@ -70,10 +69,14 @@ __device__ inline int u512_cmp(const U512& a, const U512& b) {
     return 0;
 }
 
-// A <= k^2 * V, exactly.  A and V below 2^128; k as described by kx.
-__device__ inline bool le_k2(u128 A, u128 V, const KExact& kx) {
-    if (kx.mode == 1) return A == 0;   // k^2 * V < 1 for every V < 2^128
-    if (kx.mode == 2) return true;     // no outlier can exist (Samuelson)
+__device__ inline int bitlen_u128(u128 v) {
+    uint64_t hi = (uint64_t)(v >> 64), lo = (uint64_t)v;
+    if (hi) return 128 - __clzll((long long)hi);
+    return lo ? 64 - __clzll((long long)lo) : 0;
+}
+
+// A <= k^2 * V in 512-bit integers (the general case)
+__device__ inline bool le_k2_wide(u128 A, u128 V, const KExact& kx) {
     u128 mk2 = ((u128)kx.mk2_hi << 64) | kx.mk2_lo;
     U512 rhs = u512_mul128(mk2, V);
     U512 lhs = u512_from(A);
@@ -82,6 +85,24 @@ __device__ inline bool le_k2(u128 A, u128 V, const KExact& kx) {
     else
         lhs = u512_shl(lhs, -2 * kx.ek);
     return u512_cmp(lhs, rhs) <= 0;
+}
+
+// A <= k^2 * V, exactly.  A and V below 2^128; k as described by kx.  The
+// comparison runs in 128-bit integers when both sides provably fit, else in
+// 512-bit integers.
+__device__ inline bool le_k2(u128 A, u128 V, const KExact& kx) {
+    if (kx.mode == 1) return A == 0;   // k^2 * V < 1 for every V < 2^128
+    if (kx.mode == 2) return true;     // no outlier can exist (Samuelson)
+    u128 mk2 = ((u128)kx.mk2_hi << 64) | kx.mk2_lo;
+    const int lv = bitlen_u128(V);
+    if (kx.ek >= 0) {
+        const int s = 2 * kx.ek;
+        if (kx.mk2_bits + lv + s <= 127) return A <= ((mk2 * V) << s);
+    } else {
+        const int s = -2 * kx.ek;
+        if (bitlen_u128(A) + s <= 127 && kx.mk2_bits + lv <= 127) return (A << s) <= mk2 * V;
+    }
+    return le_k2_wide(A, V, kx);
 }
 
 // num / den rounded to nearest, ties to even (den > 0, den < 2^62)
@@ -103,34 +124,12 @@ __device__ inline int64_t ceil_div(int64_t a, int64_t b) {  // b > 0
     return q;
 }
 
-// uint8 TD cut of one row with n samples, S1 = sum x, S2 = sum x^2: the set of
-// byte values that are NOT outliers is the integer interval [*lo, *hi]
-// (*lo > *hi when it is empty).
-__device__ inline void td_bounds_u8(uint64_t n, uint64_t S1, uint64_t S2, const KExact& kx,
-                                    int* lo, int* hi) {
-    u128 D = (u128)n * S2 - (u128)S1 * S1;
-    // x passes on the high side when n*x - S1 <= 0 or (n*x - S1)^2 <= k^2 D
-    auto ok_hi = [&](int64_t x) -> bool {
-        i128 d = (i128)n * x - (i128)S1;
-        if (d <= 0) return true;
-        return le_k2((u128)d * (u128)d, D, kx);
-    };
-    auto ok_lo = [&](int64_t x) -> bool {
-        i128 d = (i128)S1 - (i128)n * x;
-        if (d <= 0) return true;
-        return le_k2((u128)d * (u128)d, D, kx);
-    };
-    double mu = (double)S1 / (double)n;
-    double spread = kx.mode == 0 ? kx.k * sqrt((double)D) / (double)n : (kx.mode == 2 ? 512.0 : 0.0);
-    double eh = floor(mu + spread), el = ceil(mu - spread);
-    int64_t h = eh > 256.0 ? 256 : (eh < -1.0 ? -1 : (int64_t)eh);
-    int64_t l = el > 256.0 ? 256 : (el < -1.0 ? -1 : (int64_t)el);
-    while (h < 256 && ok_hi(h + 1)) h++;
-    while (h > -1 && !ok_hi(h)) h--;
-    while (l > -1 && ok_lo(l - 1)) l--;
-    while (l < 256 && !ok_lo(l)) l++;
-    *lo = l < 0 ? 0 : (int)l;
-    *hi = h > 255 ? 255 : (int)h;
+// TD test of one uint8 value v in a row with n samples, S1 = sum x and
+// D = n*S2 - S1^2: true when v is NOT an outlier, (n*v - S1)^2 <= k^2 * D.
+__device__ inline bool td_keeps_u8(uint64_t n, uint64_t S1, u128 D, uint32_t v, const KExact& kx) {
+    i128 d = (i128)n * v - (i128)S1;
+    u128 a = d < 0 ? (u128)(-d) : (u128)d;
+    return le_k2(a * a, D, kx);
 }
 
 // FD cut of one time sample: the largest z in [0, zcap] with C*z^2 <= k^2 SZ2;

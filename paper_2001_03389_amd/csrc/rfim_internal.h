@@ -20,6 +20,8 @@ struct KExact {
     uint64_t mk2_lo, mk2_hi;
     int32_t ek;
     int32_t mode;
+    int32_t mk2_bits;  // bit length of mk^2
+    int32_t pad;
     double k;  // the double itself, for estimates only
 };
 
@@ -58,8 +60,10 @@ struct DevBeam {
 hipError_t launch_td_rows_u8(const DevBeam* d_beams, int nbeams, int64_t total_rows,
                              const Segment& seg, uint32_t* d_rec, unsigned long long* d_counts,
                              int count_stride, hipStream_t s);
+// vec: every FD step's per-lane bin share is a multiple of 16 bytes (see
+// fd_vec_ok) so the 16-byte LDS path applies
 hipError_t launch_fused_u8(const DevBeam* d_beams, int nbeams, int64_t total_tiles,
-                           const Segment& seg, const uint32_t* d_rec, size_t lds_bytes,
+                           const Segment& seg, const uint32_t* d_rec, size_t lds_bytes, bool vec,
                            unsigned long long* d_counts, int count_stride, hipStream_t s);
 hipError_t launch_zero_u64(unsigned long long* p, int64_t n, hipStream_t s);
 

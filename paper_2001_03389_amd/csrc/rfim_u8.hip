@@ -4,17 +4,21 @@
 //  * k_td_rows_u8 -- one work-group per channel row.  Builds the row's exact
 //    256-bin histogram (every TD statistic of a uint8 row is a function of it:
 //    S1, S2, the lower median), then runs every TD step of the run on the
-//    histogram alone: the cut interval of step j is computed exactly, the
-//    counts outside it move to the replacement value's bin, and step j+1 sees
-//    the modified row without another pass over the data.  The result is a
-//    per-row record of the composite map (nested intervals plus the value and
-//    flag byte a sample gets when it first falls outside them).
-//  * k_fused_u8 -- one work-group per (beam, time tile).  Streams a
-//    [C x Tt] tile from HBM, applies each row's TD map, stores it transposed in
-//    LDS ([Tt][C], channels contiguous) and runs every FD step of the run on
-//    the tile: per time sample, bin sums, the exact sum of squared mean-
-//    corrected values, the exact cut and the replacement.  It then writes the
-//    tile (and flag bits) back.
+//    histogram alone: all 256 byte values are tested against the exact cut in
+//    parallel, the counts of the values cut move to the replacement value's bin,
+//    and step j+1 sees the modified row without another pass over the data.  The
+//    result is a per-row record of the composite map: nested intervals, plus the
+//    value and flag byte a sample gets when it first falls outside them.
+//  * k_fused_u8 -- one work-group per (beam, time tile).  Streams a [C x Tt]
+//    tile from HBM four rows at a time, transposes 4x4 byte blocks in registers
+//    and stores the tile in LDS as [Tt][C] (channels contiguous).  Samples a TD
+//    step cuts are rare: a byte-parallel mask finds them and an LDS worklist
+//    applies their TD maps.  Every FD step then runs on the LDS tile: per time
+//    sample, dot4 bin sums and sums of squares, the exact sum of squared mean-
+//    corrected values, the exact cut and a byte-select replacement.  The tile is
+//    transposed back and written out.
+#include <algorithm>
+
 #include "rfim_exact.h"
 
 namespace rfim {
@@ -45,33 +49,6 @@ __device__ inline uint64_t wave_sum_u64(uint64_t v) {
     return v;
 }
 
-// block-wide sum of one u64 per thread (256 threads, 4 waves)
-__device__ inline uint64_t block_sum_u64(uint64_t v, uint64_t* red) {
-    v = wave_sum_u64(v);
-    int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    __syncthreads();
-    if (lane == 0) red[wave] = v;
-    __syncthreads();
-    return red[0] + red[1] + red[2] + red[3];
-}
-
-// exclusive prefix sum over the 256 threads (u32 values)
-__device__ inline uint32_t block_excl_scan_u32(uint32_t v, uint32_t* red) {
-    int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    uint32_t incl = v;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        uint32_t t = __shfl_up(incl, o, 64);
-        if (lane >= o) incl += t;
-    }
-    __syncthreads();
-    if (lane == 63) red[wave] = incl;
-    __syncthreads();
-    uint32_t base = 0;
-    for (int w = 0; w < wave; w++) base += red[w];
-    return base + incl - v;
-}
-
 // XCD-aware work-group order: the hardware deals work-groups round-robin to
 // the 8 XCDs; give each XCD a contiguous range of tiles so that neighbouring
 // tiles (which share L2 lines of a row) are handled by the same XCD's L2.
@@ -82,102 +59,254 @@ __device__ inline int64_t xcd_remap(int64_t i, int64_t n) {
     return x * q + (x < r ? x : r) + j;
 }
 
+// Bytes of x outside [lo, hi] (0 <= lo, hi <= 255; lo > hi means empty) as
+// 0xFF, the others as 0x00.  Works on the even and odd bytes as 16-bit lanes:
+// lane + (0x8000 - lo) has bit 15 set iff lane >= lo, lane + (0x7FFF - hi) has
+// it set iff lane > hi; v_perm replicates each lane's bit 15 into a byte.
+__device__ inline uint32_t outside_mask(uint32_t x, uint32_t klo, uint32_t khi) {
+    const uint32_t e = x & 0x00FF00FFu;
+    const uint32_t o = (x >> 8) & 0x00FF00FFu;
+    const uint32_t oe = ~(e + klo) | (e + khi);
+    const uint32_t oo = ~(o + klo) | (o + khi);
+    return __builtin_amdgcn_perm(oo, oe, 0x0B090A08u);
+}
+
+__device__ inline uint32_t klo_of(uint32_t lo) { return (0x8000u - lo) * 0x00010001u; }
+__device__ inline uint32_t khi_of(uint32_t hi) { return (0x7FFFu - hi) * 0x00010001u; }
+
+// 4x4 byte transpose: y[j] byte i = x[i] byte j (its own inverse)
+__device__ inline void transpose4(const uint32_t x[4], uint32_t y[4]) {
+    const uint32_t t0 = __builtin_amdgcn_perm(x[1], x[0], 0x06020400u);
+    const uint32_t t1 = __builtin_amdgcn_perm(x[1], x[0], 0x07030501u);
+    const uint32_t t2 = __builtin_amdgcn_perm(x[3], x[2], 0x06020400u);
+    const uint32_t t3 = __builtin_amdgcn_perm(x[3], x[2], 0x07030501u);
+    y[0] = __builtin_amdgcn_perm(t2, t0, 0x05040100u);
+    y[1] = __builtin_amdgcn_perm(t3, t1, 0x05040100u);
+    y[2] = __builtin_amdgcn_perm(t2, t0, 0x07060302u);
+    y[3] = __builtin_amdgcn_perm(t3, t1, 0x07060302u);
+}
+
+// load 4 bytes of a row starting at sample t (bytes at or past T read as 0)
+__device__ inline uint32_t load4(const uint8_t* p, int64_t t, int64_t T) {
+    if (t + 3 < T && (((uintptr_t)p) & 3) == 0) return *(const uint32_t*)p;
+    uint32_t v = 0;
+#pragma unroll
+    for (int j = 0; j < 4; j++)
+        if (t + j < T) v |= (uint32_t)p[j] << (8 * j);
+    return v;
+}
+
+__device__ inline void store4(uint8_t* p, uint32_t v, int64_t t, int64_t T) {
+    if (t + 3 < T && (((uintptr_t)p) & 3) == 0) {
+        *(uint32_t*)p = v;
+        return;
+    }
+#pragma unroll
+    for (int j = 0; j < 4; j++)
+        if (t + j < T) p[j] = (uint8_t)(v >> (8 * j));
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// TD statistics and decisions, one wave per row (4 rows per work-group)
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr int kHistCopies = 4;     // per wave, lane & 3 picks the copy
+constexpr int kHistPitch = 260;    // words per copy (offsets the banks of copies)
+constexpr int kRowsPerWG = kBlock / 64;
+
+// Sum over the 64 lanes with DPP row rotations (every lane of a 16-lane row
+// ends with the row sum) and four lane reads; the result is wave-uniform.
+__device__ inline uint32_t wave_sum_u32(uint32_t v) {
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x128, 0xf, 0xf, false);  // row_ror:8
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x124, 0xf, 0xf, false);  // row_ror:4
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x122, 0xf, 0xf, false);  // row_ror:2
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x121, 0xf, 0xf, false);  // row_ror:1
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, 0) + (uint32_t)__builtin_amdgcn_readlane((int)v, 16) +
+           (uint32_t)__builtin_amdgcn_readlane((int)v, 32) + (uint32_t)__builtin_amdgcn_readlane((int)v, 48);
+}
+
+// wave sum of u64 values whose total is known to fit
+__device__ inline uint64_t wave_sum_u64_split(uint64_t v) {
+    // 3 x 22-bit slices: each slice sum stays below 2^28 for 64 lanes
+    const uint32_t a = wave_sum_u32((uint32_t)(v & 0x3FFFFFu));
+    const uint32_t b = wave_sum_u32((uint32_t)((v >> 22) & 0x3FFFFFu));
+    const uint32_t c = wave_sum_u32((uint32_t)(v >> 44));
+    return (uint64_t)a + ((uint64_t)b << 22) + ((uint64_t)c << 44);
+}
+
+// num / den rounded to nearest, ties to even, for num < 2^53 and den < 2^32:
+// FP64 quotient, then an exact integer correction
+__device__ inline uint64_t rn_div_small(uint64_t num, uint64_t den) {
+    uint64_t q = (uint64_t)((double)num / (double)den);
+    while (q * den > num) q--;
+    while ((q + 1) * den <= num) q++;
+    const uint64_t r = num - q * den;
+    if (2 * r > den || (2 * r == den && (q & 1))) q++;
+    return q;
+}
+
+__device__ inline void hist4(uint32_t* h, uint32_t v) {
+    atomicAdd(&h[v & 255u], 1u);
+    atomicAdd(&h[(v >> 8) & 255u], 1u);
+    atomicAdd(&h[(v >> 16) & 255u], 1u);
+    atomicAdd(&h[v >> 24], 1u);
+}
+
 }  // namespace
 
 __global__ __launch_bounds__(kBlock) void k_td_rows_u8(const DevBeam* __restrict__ beams,
-                                                       int nbeams, Segment seg,
+                                                       int nbeams, int64_t total_rows, Segment seg,
                                                        uint32_t* __restrict__ rec,
                                                        unsigned long long* __restrict__ counts,
                                                        int count_stride) {
-    __shared__ uint32_t hist[4][256];
-    __shared__ uint64_t red64[4];
-    __shared__ uint32_t red32[4];
-    __shared__ int s_lo[kMaxSteps], s_hi[kMaxSteps], s_r[kMaxSteps];
-    __shared__ int s_med;
+    __shared__ uint32_t hist_all[kRowsPerWG][kHistCopies * kHistPitch];
+    __shared__ int s_lo_all[kRowsPerWG][kMaxSteps], s_hi_all[kRowsPerWG][kMaxSteps],
+        s_r_all[kRowsPerWG][kMaxSteps];
 
-    const int tid = threadIdx.x, wave = tid >> 6;
-    const int64_t g = blockIdx.x;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t g = (int64_t)blockIdx.x * kRowsPerWG + wave;
+    if (g >= total_rows) return;
+    uint32_t* hist = hist_all[wave];
+    int* s_lo = s_lo_all[wave];
+    int* s_hi = s_hi_all[wave];
+    int* s_r = s_r_all[wave];
     const int b = find_beam_by_row(beams, nbeams, g);
     const DevBeam& bm = beams[b];
     const int64_t c = g - bm.row0;
     const int64_t T = bm.T;
     const uint8_t* row = (const uint8_t*)bm.in + c * bm.stride;
 
-    for (int i = tid; i < 4 * 256; i += kBlock) (&hist[0][0])[i] = 0;
-    __syncthreads();
+    for (int i = lane; i < kHistCopies * kHistPitch; i += 64) hist[i] = 0;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
 
-    // histogram: unaligned head bytes, aligned dwords, tail bytes
+    // histogram: bytes up to a dword boundary, then 16-byte loads (dword
+    // aligned), then the tail bytes
+    uint32_t* h = hist + (lane & 3) * kHistPitch;
     int64_t head = (int64_t)((4 - ((uintptr_t)row & 3)) & 3);
     if (head > T) head = T;
-    for (int64_t i = tid; i < head; i += kBlock) atomicAdd(&hist[wave][row[i]], 1u);
-    const int64_t nd = (T - head) >> 2;
-    const uint32_t* rw = (const uint32_t*)(row + head);
-    for (int64_t i = tid; i < nd; i += kBlock) {
-        uint32_t v = __builtin_nontemporal_load(rw + i);
-        atomicAdd(&hist[wave][v & 255u], 1u);
-        atomicAdd(&hist[wave][(v >> 8) & 255u], 1u);
-        atomicAdd(&hist[wave][(v >> 16) & 255u], 1u);
-        atomicAdd(&hist[wave][v >> 24], 1u);
+    if (lane < head) atomicAdd(&h[row[lane]], 1u);
+    const int64_t n16 = (T - head) >> 4;
+    const uint8_t* body = row + head;
+    int64_t i = lane;
+    for (; i + 64 < n16; i += 128) {
+        const uint4 v0 = *(const uint4*)(body + 16 * i);
+        const uint4 v1 = *(const uint4*)(body + 16 * (i + 64));
+        hist4(h, v0.x); hist4(h, v0.y); hist4(h, v0.z); hist4(h, v0.w);
+        hist4(h, v1.x); hist4(h, v1.y); hist4(h, v1.z); hist4(h, v1.w);
     }
-    for (int64_t i = head + 4 * nd + tid; i < T; i += kBlock) atomicAdd(&hist[wave][row[i]], 1u);
-    __syncthreads();
+    for (; i < n16; i += 64) {
+        const uint4 v0 = *(const uint4*)(body + 16 * i);
+        hist4(h, v0.x); hist4(h, v0.y); hist4(h, v0.z); hist4(h, v0.w);
+    }
+    for (int64_t k = head + 16 * n16 + lane; k < T; k += 64) atomicAdd(&h[row[k]], 1u);
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    __builtin_amdgcn_wave_barrier();
 
-    // thread v owns histogram bin v from here on
-    const uint32_t v = (uint32_t)tid;
-    uint32_t hv = hist[0][v] + hist[1][v] + hist[2][v] + hist[3][v];
+    // lane l owns the byte values 4l .. 4l+3
+    uint32_t hv[4];
+#pragma unroll
+    for (int u = 0; u < 4; u++) {
+        const int v = 4 * lane + u;
+        uint32_t t = 0;
+#pragma unroll
+        for (int cp = 0; cp < kHistCopies; cp++) t += hist[cp * kHistPitch + v];
+        hv[u] = t;
+    }
     const uint64_t n = (uint64_t)T;
 
     for (int j = 0; j < seg.n_td; j++) {
         const SegStep& st = seg.td[j];
-        uint64_t S1 = block_sum_u64((uint64_t)hv * v, red64);
-        uint64_t S2 = block_sum_u64((uint64_t)hv * v * v, red64);
+        uint64_t S1 = 0, S2 = 0;
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            const uint64_t v = 4 * lane + u;
+            S1 += (uint64_t)hv[u] * v;
+            S2 += (uint64_t)hv[u] * v * v;
+        }
+        S1 = wave_sum_u64_split(S1);   // below 2^39 for n < 2^31
+        S2 = wave_sum_u64_split(S2);   // below 2^47 for n < 2^31
+        int r;
         if (st.replace == RFIM_REPLACE_MEDIAN) {
-            // lower median: the bin holding rank floor((n-1)/2)
-            uint32_t before = block_excl_scan_u32(hv, red32);
-            uint64_t q = (n - 1) / 2;
-            if (hv > 0 && before <= q && q < (uint64_t)before + hv) s_med = (int)v;
+            // lower median: the byte value holding rank floor((n-1)/2)
+            const uint32_t mine = hv[0] + hv[1] + hv[2] + hv[3];
+            uint32_t incl = mine;
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const uint32_t t = __shfl_up(incl, o, 64);
+                if (lane >= o) incl += t;
+            }
+            const uint64_t q = (n - 1) / 2;
+            uint32_t before = incl - mine;
+            int med = -1;
+#pragma unroll
+            for (int u = 0; u < 4; u++) {
+                if (hv[u] > 0 && before <= q && q < (uint64_t)before + hv[u]) med = 4 * lane + u;
+                before += hv[u];
+            }
+            const uint64_t mb = __ballot(med >= 0);
+            r = __shfl(med, __ffsll((unsigned long long)mb) - 1, 64);
+        } else {
+            r = (int)rn_div_small(S1, n);
         }
-        __syncthreads();
-        if (tid == 0) {
-            int lo, hi;
-            td_bounds_u8(n, S1, S2, st.kx, &lo, &hi);
-            s_lo[j] = lo;
-            s_hi[j] = hi;
-            s_r[j] = st.replace == RFIM_REPLACE_MEDIAN ? s_med : (int)rn_div_u64(S1, n);
+        // every byte value is tested exactly
+        const u128 D = (u128)n * S2 - (u128)S1 * S1;
+        bool keep[4];
+        int lo = 256, hi = -1;
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            keep[u] = td_keeps_u8(n, S1, D, 4 * lane + u, st.kx);
+            const uint64_t km = __ballot(keep[u]);
+            if (km) {
+                lo = min(lo, 4 * (__ffsll((unsigned long long)km) - 1) + u);
+                hi = max(hi, 4 * (63 - __clzll((long long)km)) + u);
+            }
         }
-        __syncthreads();
-        const int lo = s_lo[j], hi = s_hi[j], r = s_r[j];
-        const bool out = (int)v < lo || (int)v > hi;
-        uint64_t moved = block_sum_u64(out ? hv : 0u, red64);
-        if (out) hv = 0;
-        if ((int)v == r) hv += (uint32_t)moved;
-        if (tid == 0 && counts && st.bit >= 0 && moved)
-            atomicAdd(&counts[(int64_t)bm.cidx * count_stride + st.bit], (unsigned long long)moved);
+        uint32_t moved32 = 0;
+#pragma unroll
+        for (int u = 0; u < 4; u++) moved32 += keep[u] ? 0u : hv[u];
+        const uint64_t moved = wave_sum_u32(moved32);   // at most n < 2^31
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            if (!keep[u]) hv[u] = 0;
+            if (4 * lane + u == r) hv[u] += (uint32_t)moved;
+        }
+        if (lane == 0) {
+            s_lo[j] = lo <= hi ? lo : 1;   // kept values form [lo, hi]; empty as [1, 0]
+            s_hi[j] = lo <= hi ? hi : 0;
+            s_r[j] = r;
+            if (counts && st.bit >= 0 && moved)
+                atomicAdd(&counts[(int64_t)bm.cidx * count_stride + st.bit], (unsigned long long)moved);
+        }
     }
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    __builtin_amdgcn_wave_barrier();
 
     // composite record of the run, one u32 per step:
     //   [7:0] L_j, [15:8] H_j  -- nested interval: a sample stays untouched
     //                             through step j iff L_j <= x <= H_j
-    //   [23:16] value a sample first flagged at step j ends with
+    //   [23:16] value a sample first cut at step j ends with
     //   [31:24] flag bits it collects (step j and any later step that cuts
     //           the replacement value)
-    if (tid < seg.n_td) {
-        const int j = tid;
+    if (lane < seg.n_td) {
+        const int j = lane;
         int L = 0, H = 255;
-        for (int i = 0; i <= j; i++) {
-            L = max(L, s_lo[i]);
-            H = min(H, s_hi[i]);
+        for (int k = 0; k <= j; k++) {
+            L = max(L, s_lo[k]);
+            H = min(H, s_hi[k]);
         }
         int val = s_r[j];
         uint32_t f = seg.td[j].bit >= 0 ? (1u << seg.td[j].bit) : 0u;
-        for (int i = j + 1; i < seg.n_td; i++) {
-            if (val < s_lo[i] || val > s_hi[i]) {
-                val = s_r[i];
-                if (seg.td[i].bit >= 0) f |= 1u << seg.td[i].bit;
+        for (int k = j + 1; k < seg.n_td; k++) {
+            if (val < s_lo[k] || val > s_hi[k]) {
+                val = s_r[k];
+                if (seg.td[k].bit >= 0) f |= 1u << seg.td[k].bit;
             }
         }
-        // an empty interval is encoded as L = 1, H = 0
-        if (L > H) {
+        if (L > H) {  // empty interval: every value is cut
             L = 1;
             H = 0;
         }
@@ -187,7 +316,12 @@ __global__ __launch_bounds__(kBlock) void k_td_rows_u8(const DevBeam* __restrict
 
 namespace {
 
-// group of G consecutive lanes (G a power of two <= 64): sum of a u128
+// group of G consecutive lanes (G a power of two <= 64): sum of u64 values
+__device__ inline uint64_t group_sum_u64(uint64_t v, int G) {
+    for (int o = 1; o < G; o <<= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
 __device__ inline u128 group_sum_u128(u128 v, int G) {
     uint64_t lo = (uint64_t)v, hi = (uint64_t)(v >> 64);
     for (int o = 1; o < G; o <<= 1) {
@@ -200,193 +334,560 @@ __device__ inline u128 group_sum_u128(u128 v, int G) {
     return ((u128)hi << 64) | lo;
 }
 
-// lower median (rank floor((n-1)/2)) of n bytes spaced `step` apart in LDS:
-// the largest value v with #{x < v} <= rank, found bit by bit
-__device__ inline int lds_lower_median_u8(const uint8_t* p, int64_t n, int64_t step) {
+// Full TD composite map of one byte (records r[0..m) of its row)
+__device__ inline uint32_t td_map_byte(uint32_t x, const uint32_t* __restrict__ r, int m,
+                                       uint32_t* fl) {
+    uint32_t out = x, f = 0;
+    for (int j = m - 1; j >= 0; j--) {
+        const uint32_t e = r[j];
+        const uint32_t L = e & 255u, H = (e >> 8) & 255u;
+        if (x < L || x > H) {
+            out = (e >> 16) & 255u;
+            f = e >> 24;
+        }
+    }
+    *fl = f;
+    return out;
+}
+
+// lower median (rank floor((n-1)/2)) of the n bytes at p: the largest value v
+// with #{x < v} <= rank, found bit by bit
+__device__ inline uint32_t lds_lower_median_u8(const uint8_t* p, int64_t n) {
     const int64_t rank = (n - 1) / 2;
-    int prefix = 0;
+    uint32_t prefix = 0;
     for (int bit = 7; bit >= 0; bit--) {
-        int cand = prefix | (1 << bit);
+        const uint32_t cand = prefix | (1u << bit);
         int64_t below = 0;
-        for (int64_t i = 0; i < n; i++) below += p[i * step] < cand;
+        if ((n & 3) == 0 && (((uintptr_t)p) & 3) == 0) {
+            const uint32_t kc = klo_of(cand);
+            for (int64_t i = 0; i < n; i += 4) {
+                const uint32_t x = *(const uint32_t*)(p + i);
+                // bytes >= cand have bit 15 of their lane set after adding kc
+                const uint32_t e = (x & 0x00FF00FFu) + kc, o = ((x >> 8) & 0x00FF00FFu) + kc;
+                below += 4 - (int64_t)__popc((e & 0x80008000u) | ((o & 0x80008000u) >> 1));
+            }
+        } else {
+            for (int64_t i = 0; i < n; i++) below += p[i] < cand;
+        }
         if (below <= rank) prefix = cand;
     }
     return prefix;
 }
 
-__device__ inline uint8_t td_map(uint8_t x, const uint32_t* r, int m, uint8_t* fl) {
-    uint8_t out = x, f = 0;
-    for (int j = m - 1; j >= 0; j--) {
-        uint32_t e = r[j];
-        int L = e & 255, H = (e >> 8) & 255;
-        if ((int)x < L || (int)x > H) {
-            out = (uint8_t)(e >> 16);
-            f = (uint8_t)(e >> 24);
+constexpr int kExcCap = 768;  // TD exception worklist entries per work-group
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// TD apply + FD steps on an LDS tile, one work-group per (beam, time tile)
+// ---------------------------------------------------------------------------
+namespace {
+
+struct TileCtx {
+    const uint8_t* in;
+    uint8_t* out;
+    uint8_t* flags;
+    const uint32_t* rec;   // this beam's TD records, [row][n_td]
+    int64_t C, T, stride, t0;
+    int Tt, Cp, tw, tw_log, n_td;
+    int64_t nq4;
+};
+
+// the 4 rows c0..c0+3 of dword w of the tile; rows past C read as 0
+template <bool INTERIOR>
+__device__ inline void load_quad(const TileCtx& k, const uint8_t* base, int64_t c0, int w, uint32_t x[4]) {
+    const int64_t t = k.t0 + 4 * w;
+#pragma unroll
+    for (int i = 0; i < 4; i++) {
+        if (INTERIOR) {
+            const int64_t c = c0 + i < k.C ? c0 + i : k.C - 1;
+            const uint32_t v = *(const uint32_t*)(base + c * k.stride + t);
+            x[i] = c0 + i < k.C ? v : 0u;
+        } else {
+            x[i] = (c0 + i < k.C) ? load4(base + (c0 + i) * k.stride + t, t, k.T) : 0u;
         }
     }
-    *fl |= f;
-    return out;
+}
+
+template <bool INTERIOR>
+__device__ inline void store_quad(const TileCtx& k, uint8_t* base, int64_t c0, int w, const uint32_t x[4]) {
+    const int64_t t = k.t0 + 4 * w;
+#pragma unroll
+    for (int i = 0; i < 4; i++) {
+        if (c0 + i >= k.C) continue;
+        if (INTERIOR)
+            *(uint32_t*)(base + (c0 + i) * k.stride + t) = x[i];
+        else
+            store4(base + (c0 + i) * k.stride + t, x[i], t, k.T);
+    }
+}
+
+// bytes of the dword at sample t that lie inside the batch
+__device__ inline uint32_t valid_bytes(int64_t t, int64_t T) {
+    return t + 3 < T ? 0xFFFFFFFFu : (t >= T ? 0u : (0xFFFFFFFFu >> (8 * (4 - (T - t)))));
+}
+
+// Phase 1 body for one row-quad task: 4 rows in, TD fast check (exceptions
+// to the worklist), 4x4 transpose, LDS tile [Tt][Cp]
+template <bool INTERIOR>
+__device__ inline void tile_load_task(const TileCtx& k, int64_t idx, uint8_t* tile, uint8_t* ftile,
+                                      bool want_flags, bool or_flags, uint32_t* exc_pos,
+                                      uint32_t* exc_n) {
+    const int64_t q4 = idx >> k.tw_log;
+    const int w = (int)(idx & (k.tw - 1));
+    const int64_t c0 = 4 * q4;
+    uint32_t x[4], y[4];
+    load_quad<INTERIOR>(k, k.in, c0, w, x);
+    if (k.n_td > 0) {
+        const uint32_t valid = INTERIOR ? 0xFFFFFFFFu : valid_bytes(k.t0 + 4 * w, k.T);
+#pragma unroll
+        for (int i = 0; i < 4; i++) {
+            const int64_t c = c0 + i < k.C ? c0 + i : k.C - 1;
+            const uint32_t e = k.rec[c * k.n_td + (k.n_td - 1)];
+            uint32_t m = outside_mask(x[i], klo_of(e & 255u), khi_of((e >> 8) & 255u)) & valid;
+            if (c0 + i >= k.C) m = 0;
+            if (m) {
+                const uint32_t slot = atomicAdd(exc_n, 1u);
+                if (slot < (uint32_t)kExcCap) exc_pos[slot] = ((uint32_t)(c0 + i) << 8) | (uint32_t)w;
+            }
+        }
+    }
+    transpose4(x, y);
+#pragma unroll
+    for (int j = 0; j < 4; j++) *(uint32_t*)(tile + (size_t)(4 * w + j) * k.Cp + c0) = y[j];
+    if (want_flags) {
+        uint32_t fx[4] = {0u, 0u, 0u, 0u}, fy[4];
+        if (or_flags) load_quad<INTERIOR>(k, k.flags, c0, w, fx);
+        transpose4(fx, fy);
+#pragma unroll
+        for (int j = 0; j < 4; j++) *(uint32_t*)(ftile + (size_t)(4 * w + j) * k.Cp + c0) = fy[j];
+    }
+}
+
+// Phase 1 body for a 4-row x 16-sample task of an interior tile whose rows
+// are dword aligned: one 16-byte load per row
+__device__ inline void tile_load_task16(const TileCtx& k, int64_t idx, uint8_t* tile, uint8_t* ftile,
+                                        bool want_flags, bool or_flags, uint32_t* exc_pos,
+                                        uint32_t* exc_n) {
+    const int tq_log = k.tw_log - 2;              // 16-sample chunks per tile row
+    const int64_t q4 = idx >> tq_log;
+    const int w16 = (int)(idx & ((1 << tq_log) - 1));
+    const int64_t c0 = 4 * q4;
+    uint4 x[4];
+#pragma unroll
+    for (int i = 0; i < 4; i++) {
+        const int64_t c = c0 + i < k.C ? c0 + i : k.C - 1;
+        x[i] = *(const uint4*)(k.in + c * k.stride + k.t0 + 16 * w16);
+        if (c0 + i >= k.C) x[i] = make_uint4(0u, 0u, 0u, 0u);
+    }
+    if (k.n_td > 0) {
+#pragma unroll
+        for (int i = 0; i < 4; i++) {
+            if (c0 + i >= k.C) continue;
+            const uint32_t e = k.rec[(c0 + i) * k.n_td + (k.n_td - 1)];
+            const uint32_t klo = klo_of(e & 255u), khi = khi_of((e >> 8) & 255u);
+            const uint32_t m0 = outside_mask(x[i].x, klo, khi), m1 = outside_mask(x[i].y, klo, khi);
+            const uint32_t m2 = outside_mask(x[i].z, klo, khi), m3 = outside_mask(x[i].w, klo, khi);
+            if (m0 | m1 | m2 | m3) {
+                const uint32_t mm[4] = {m0, m1, m2, m3};
+#pragma unroll
+                for (int j = 0; j < 4; j++) {
+                    if (!mm[j]) continue;
+                    const uint32_t slot = atomicAdd(exc_n, 1u);
+                    if (slot < (uint32_t)kExcCap)
+                        exc_pos[slot] = ((uint32_t)(c0 + i) << 8) | (uint32_t)(4 * w16 + j);
+                }
+            }
+        }
+    }
+    uint32_t a[4], y[4];
+#define RFIM_T16(F, J)                                                                      \
+    a[0] = x[0].F; a[1] = x[1].F; a[2] = x[2].F; a[3] = x[3].F;                             \
+    transpose4(a, y);                                                                       \
+    for (int jj = 0; jj < 4; jj++)                                                          \
+        *(uint32_t*)(tile + (size_t)(16 * w16 + 4 * (J) + jj) * k.Cp + c0) = y[jj];
+    RFIM_T16(x, 0) RFIM_T16(y, 1) RFIM_T16(z, 2) RFIM_T16(w, 3)
+#undef RFIM_T16
+    if (want_flags) {
+        for (int j = 0; j < 4; j++) {
+            uint32_t fx[4] = {0u, 0u, 0u, 0u}, fy[4];
+            if (or_flags) load_quad<true>(k, k.flags, c0, 4 * w16 + j, fx);
+            transpose4(fx, fy);
+            for (int jj = 0; jj < 4; jj++)
+                *(uint32_t*)(ftile + (size_t)(16 * w16 + 4 * j + jj) * k.Cp + c0) = fy[jj];
+        }
+    }
+}
+
+// Phase 3 body for a 4-row x 16-sample task of an interior tile
+__device__ inline void tile_store_task16(const TileCtx& k, int64_t idx, const uint8_t* tile,
+                                         const uint8_t* ftile, bool want_flags) {
+    const int tq_log = k.tw_log - 2;
+    const int64_t q4 = idx >> tq_log;
+    const int w16 = (int)(idx & ((1 << tq_log) - 1));
+    const int64_t c0 = 4 * q4;
+    uint4 x[4];
+    uint32_t a[4], y[4];
+#define RFIM_S16(F, J)                                                                      \
+    for (int jj = 0; jj < 4; jj++)                                                          \
+        y[jj] = *(const uint32_t*)(tile + (size_t)(16 * w16 + 4 * (J) + jj) * k.Cp + c0);   \
+    transpose4(y, a);                                                                       \
+    x[0].F = a[0]; x[1].F = a[1]; x[2].F = a[2]; x[3].F = a[3];
+    RFIM_S16(x, 0) RFIM_S16(y, 1) RFIM_S16(z, 2) RFIM_S16(w, 3)
+#undef RFIM_S16
+#pragma unroll
+    for (int i = 0; i < 4; i++)
+        if (c0 + i < k.C) *(uint4*)(k.out + (c0 + i) * k.stride + k.t0 + 16 * w16) = x[i];
+    if (want_flags) {
+        for (int j = 0; j < 4; j++) {
+            uint32_t fy[4], fx[4];
+            for (int jj = 0; jj < 4; jj++)
+                fy[jj] = *(const uint32_t*)(ftile + (size_t)(16 * w16 + 4 * j + jj) * k.Cp + c0);
+            transpose4(fy, fx);
+            store_quad<true>(k, k.flags, c0, 4 * w16 + j, fx);
+        }
+    }
+}
+
+// Phase 3 body: transpose back and write 4 rows (and flags)
+template <bool INTERIOR>
+__device__ inline void tile_store_task(const TileCtx& k, int64_t idx, const uint8_t* tile,
+                                       const uint8_t* ftile, bool want_flags) {
+    const int64_t q4 = idx >> k.tw_log;
+    const int w = (int)(idx & (k.tw - 1));
+    const int64_t c0 = 4 * q4;
+    uint32_t y[4], x[4];
+#pragma unroll
+    for (int j = 0; j < 4; j++) y[j] = *(const uint32_t*)(tile + (size_t)(4 * w + j) * k.Cp + c0);
+    transpose4(y, x);
+    store_quad<INTERIOR>(k, k.out, c0, w, x);
+    if (want_flags) {
+#pragma unroll
+        for (int j = 0; j < 4; j++) y[j] = *(const uint32_t*)(ftile + (size_t)(4 * w + j) * k.Cp + c0);
+        transpose4(y, x);
+        store_quad<INTERIOR>(k, k.flags, c0, w, x);
+    }
+}
+
+// bytes of one dword as mapped by the TD composite map of row c (and flag bits)
+__device__ inline uint32_t td_map_dword(const TileCtx& k, int64_t c, uint32_t xv, uint32_t* fv) {
+    const uint32_t* rp = k.rec + c * k.n_td;
+    uint32_t nv = 0, f4 = 0;
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+        uint32_t f;
+        nv |= td_map_byte((xv >> (8 * j)) & 255u, rp, k.n_td, &f) << (8 * j);
+        f4 |= f << (8 * j);
+    }
+    *fv = f4;
+    return nv;
+}
+
+__device__ inline void put_dword_transposed(uint8_t* tile, const TileCtx& k, int64_t c, int w, uint32_t v) {
+#pragma unroll
+    for (int j = 0; j < 4; j++) tile[(size_t)(4 * w + j) * k.Cp + c] = (uint8_t)(v >> (8 * j));
+}
+
+__device__ inline void or_dword_transposed(uint8_t* tile, const TileCtx& k, int64_t c, int w, uint32_t v) {
+#pragma unroll
+    for (int j = 0; j < 4; j++) tile[(size_t)(4 * w + j) * k.Cp + c] |= (uint8_t)(v >> (8 * j));
 }
 
 }  // namespace
 
+// Phase 2: every FD step of the run on the LDS tile; G = 256/Tt consecutive
+// lanes own one time sample (column).  VEC: every lane's share of a bin is a
+// multiple of 16 bytes at a 16-byte boundary (the host checks), so bins are
+// read with 16-byte LDS loads and summed with dot4; otherwise bytes.
+template <bool VEC>
+__device__ inline void fd_steps(const TileCtx& k, const Segment& seg, uint8_t* tile, uint8_t* ftile,
+                                bool want_flags, bool count, unsigned long long* s_cnt) {
+    const int tid = threadIdx.x;
+    const int Tt = k.Tt;
+    const int G = kBlock / Tt;
+    const int tl = tid / G, q = tid % G;
+    const bool valid = k.t0 + tl < k.T;
+    const int64_t C = k.C;
+    uint8_t* colp = tile + (size_t)tl * k.Cp;
+    uint8_t* fcol = ftile + (size_t)tl * k.Cp;
+    for (int s = 0; s < seg.n_fd; s++) {
+        const SegStep& st = seg.fd[s];
+        const int64_t B = st.bin == 0 ? C : st.bin;
+        const int nb = (int)(C / B);
+        const int bshift = (B & (B - 1)) == 0 ? __ffsll((unsigned long long)B) - 1 : -1;
+        // lanes per bin: bins split over lanes when there are fewer bins than
+        // lanes (and, for VEC, the split stays 16-byte aligned)
+        int lpb = 1;
+        if (nb < G && (G % nb) == 0 && (B % ((VEC ? 16 : 1) * (G / nb))) == 0) lpb = G / nb;
+        const int64_t chunk = B / lpb;
+        const int first = lpb > 1 ? q / lpb : q;
+        const int bstep = lpb > 1 ? nb : G;     // lpb > 1: one bin per lane
+        const int64_t coff = lpb > 1 ? (int64_t)(q % lpb) * chunk : 0;
+        // statistics: sum over bins of B*(B*Q_b - S_b^2) = sum of Z_c^2
+        u128 sz2 = 0;
+        for (int bb = first; bb < nb; bb += bstep) {
+            const uint8_t* p = colp + (int64_t)bb * B + coff;
+            uint64_t S = 0, Q = 0;
+            if (VEC) {
+                for (int64_t i0 = 0; i0 < chunk; i0 += 65536) {
+                    uint32_t s32 = 0, q32 = 0;
+                    const int64_t i1 = min(chunk, i0 + 65536);
+                    for (int64_t i = i0; i < i1; i += 16) {
+                        const uint4 x = *(const uint4*)(p + i);
+                        s32 = __builtin_amdgcn_udot4(x.x, 0x01010101u, s32, false);
+                        s32 = __builtin_amdgcn_udot4(x.y, 0x01010101u, s32, false);
+                        s32 = __builtin_amdgcn_udot4(x.z, 0x01010101u, s32, false);
+                        s32 = __builtin_amdgcn_udot4(x.w, 0x01010101u, s32, false);
+                        q32 = __builtin_amdgcn_udot4(x.x, x.x, q32, false);
+                        q32 = __builtin_amdgcn_udot4(x.y, x.y, q32, false);
+                        q32 = __builtin_amdgcn_udot4(x.z, x.z, q32, false);
+                        q32 = __builtin_amdgcn_udot4(x.w, x.w, q32, false);
+                    }
+                    S += s32;
+                    Q += q32;
+                }
+            } else {
+                for (int64_t i = 0; i < chunk; i++) {
+                    const uint32_t x = p[i];
+                    S += x;
+                    Q += x * x;
+                }
+            }
+            if (lpb > 1) {
+                S = group_sum_u64(S, lpb);   // lanes of one bin are adjacent
+                Q = group_sum_u64(Q, lpb);
+                if (q % lpb) continue;       // count each bin once
+            }
+            sz2 += (u128)B * ((u128)B * Q - (u128)S * S);
+        }
+        sz2 = group_sum_u128(sz2, G);
+        const uint64_t z = fd_zthr(sz2, C, st.kx, (uint64_t)B * 255u);
+        const uint32_t fbit = st.bit >= 0 ? (1u << st.bit) * 0x01010101u : 0u;
+        uint64_t nflag = 0;
+        for (int bb = first; bb < nb; bb += bstep) {
+            uint8_t* p = colp + (int64_t)bb * B + coff;
+            uint8_t* fp = fcol + (int64_t)bb * B + coff;
+            // bin sum again (cheap) for the cut and the replacement
+            uint64_t S = 0;
+            if (VEC) {
+                uint32_t s32 = 0;
+                for (int64_t i = 0; i < chunk; i += 16) {
+                    const uint4 x = *(const uint4*)(p + i);
+                    s32 = __builtin_amdgcn_udot4(x.x, 0x01010101u, s32, false);
+                    s32 = __builtin_amdgcn_udot4(x.y, 0x01010101u, s32, false);
+                    s32 = __builtin_amdgcn_udot4(x.z, 0x01010101u, s32, false);
+                    s32 = __builtin_amdgcn_udot4(x.w, 0x01010101u, s32, false);
+                }
+                S = s32;
+            } else {
+                for (int64_t i = 0; i < chunk; i++) S += p[i];
+            }
+            if (lpb > 1) S = group_sum_u64(S, lpb);
+            // kept: |B*x - S| <= z  <=>  ceil((S - z)/B) <= x <= floor((S + z)/B)
+            int64_t lo, hi;
+            if (bshift >= 0) {
+                lo = -((int64_t)(z - S) >> bshift);          // ceil((S - z) / 2^bshift)
+                hi = (int64_t)(S + z) >> bshift;
+            } else {
+                lo = ceil_div((int64_t)S - (int64_t)z, B);
+                hi = floor_div((int64_t)S + (int64_t)z, B);
+            }
+            lo = lo < 0 ? 0 : lo;
+            hi = hi > 255 ? 255 : hi;
+            uint32_t klo = klo_of(1), khi = khi_of(0);   // empty interval
+            if (lo <= hi) {
+                klo = klo_of((uint32_t)lo);
+                khi = khi_of((uint32_t)hi);
+            }
+            uint32_t r;
+            if (st.replace == RFIM_REPLACE_MEDIAN) {
+                // needed only when the bin has an outlier in this column
+                uint32_t any = 0;
+                if (VEC) {
+                    for (int64_t i = 0; i < chunk; i += 4) any |= outside_mask(*(const uint32_t*)(p + i), klo, khi);
+                } else {
+                    for (int64_t i = 0; i < chunk; i++) any |= ((int64_t)p[i] < lo || (int64_t)p[i] > hi);
+                }
+                if (lpb > 1) any = (uint32_t)group_sum_u64(any ? 1u : 0u, lpb);
+                if (!any) continue;
+                // every lane of a split bin computes the same median
+                r = lds_lower_median_u8(colp + (int64_t)bb * B, B);
+            } else if (bshift >= 0) {
+                const uint64_t qv = S >> bshift, rem = S & (B - 1);
+                r = (uint32_t)(qv + ((2 * rem > (uint64_t)B || (2 * rem == (uint64_t)B && (qv & 1))) ? 1 : 0));
+            } else {
+                r = (uint32_t)rn_div_u64(S, (uint64_t)B);
+            }
+            const uint32_t rrep = r * 0x01010101u;
+            if (VEC) {
+                for (int64_t i = 0; i < chunk; i += 16) {
+                    uint4 x = *(const uint4*)(p + i);
+                    const uint32_t m0 = outside_mask(x.x, klo, khi), m1 = outside_mask(x.y, klo, khi);
+                    const uint32_t m2 = outside_mask(x.z, klo, khi), m3 = outside_mask(x.w, klo, khi);
+                    if (m0 | m1 | m2 | m3) {
+                        x.x = (x.x & ~m0) | (rrep & m0);
+                        x.y = (x.y & ~m1) | (rrep & m1);
+                        x.z = (x.z & ~m2) | (rrep & m2);
+                        x.w = (x.w & ~m3) | (rrep & m3);
+                        *(uint4*)(p + i) = x;
+                        if (want_flags) {
+                            uint4 f = *(const uint4*)(fp + i);
+                            f.x |= m0 & fbit;
+                            f.y |= m1 & fbit;
+                            f.z |= m2 & fbit;
+                            f.w |= m3 & fbit;
+                            *(uint4*)(fp + i) = f;
+                        }
+                        nflag += (__popc(m0) + __popc(m1) + __popc(m2) + __popc(m3)) >> 3;
+                    }
+                }
+            } else {
+                for (int64_t i = 0; i < chunk; i++) {
+                    if ((int64_t)p[i] < lo || (int64_t)p[i] > hi) {
+                        p[i] = (uint8_t)r;
+                        if (want_flags && st.bit >= 0) fp[i] |= (uint8_t)(1u << st.bit);
+                        nflag++;
+                    }
+                }
+            }
+        }
+        if (valid && nflag && count && st.bit >= 0) atomicAdd(&s_cnt[s], (unsigned long long)nflag);
+    }
+}
+
+// One work-group per (beam, time tile); work-groups are handed out so that
+// each XCD gets a contiguous range of tiles.
+template <bool VEC>
 __global__ __launch_bounds__(kBlock) void k_fused_u8(const DevBeam* __restrict__ beams, int nbeams,
                                                      int64_t total_tiles, Segment seg,
                                                      const uint32_t* __restrict__ rec,
                                                      unsigned long long* __restrict__ counts,
                                                      int count_stride) {
     extern __shared__ __align__(16) uint8_t lds[];
+    __shared__ uint32_t exc_pos[kExcCap];   // (row << 8) | dword index in the tile
+    __shared__ uint32_t exc_n;
     __shared__ unsigned long long s_cnt[kMaxSteps];
 
     const int tid = threadIdx.x;
     const int64_t g = xcd_remap(blockIdx.x, total_tiles);
     const int b = find_beam_by_tile(beams, nbeams, g);
     const DevBeam& bm = beams[b];
-    const int64_t C = bm.C, T = bm.T, stride = bm.stride;
-    const int Tt = bm.Tt, Cp = bm.Cp;
-    const int64_t t0 = (g - bm.tile0) * Tt;
-    const int tw = Tt >> 2;
+    TileCtx k;
+    k.in = (const uint8_t*)bm.in;
+    k.out = (uint8_t*)bm.out;
+    k.flags = bm.flags;
+    k.C = bm.C;
+    k.T = bm.T;
+    k.stride = bm.stride;
+    k.Tt = bm.Tt;
+    k.Cp = bm.Cp;
+    k.t0 = (g - bm.tile0) * k.Tt;
+    k.tw = k.Tt >> 2;
+    k.tw_log = __ffs(k.tw) - 1;
+    k.n_td = seg.n_td;
+    k.rec = rec + bm.row0 * seg.n_td;
+    k.nq4 = (k.C + 3) >> 2;
     const bool want_flags = seg.flags_mode != 0 && bm.flags != nullptr;
+    const bool or_flags = seg.flags_mode == 2;
+    const bool interior = k.t0 + k.Tt <= k.T && (k.stride & 3) == 0 &&
+                          (((uintptr_t)k.in | (uintptr_t)k.out |
+                            (want_flags ? (uintptr_t)k.flags : 0)) & 3) == 0;
     uint8_t* tile = lds;
-    uint8_t* ftile = lds + (size_t)Tt * Cp;
-    const uint8_t* in = (const uint8_t*)bm.in;
-    uint8_t* out = (uint8_t*)bm.out;
+    uint8_t* ftile = lds + (size_t)k.Tt * k.Cp;
+    const int64_t ntask = k.nq4 * k.tw;
 
     if (tid < kMaxSteps) s_cnt[tid] = 0;
+    if (tid == 0) exc_n = 0;
+    __syncthreads();
 
-    // ---- phase 1: load rows, apply the TD maps, store transposed into LDS
-    for (int64_t idx = tid; idx < C * tw; idx += kBlock) {
-        const int64_t c = idx / tw;
-        const int w = (int)(idx - c * tw);
-        const int64_t t = t0 + 4 * w;
-        const uint8_t* src = in + c * stride + t;
-        uint8_t x[4], f[4] = {0, 0, 0, 0};
-        if (t + 3 < T && (((uintptr_t)src) & 3) == 0) {
-            uint32_t d = *(const uint32_t*)src;
-            x[0] = d & 255; x[1] = (d >> 8) & 255; x[2] = (d >> 16) & 255; x[3] = d >> 24;
+    // ---- phase 1: rows in, TD fast check, transposed into LDS
+    const bool wide = interior && (k.Tt & 15) == 0;
+    if (wide) {
+        for (int64_t idx = tid; idx < ntask / 4; idx += kBlock)
+            tile_load_task16(k, idx, tile, ftile, want_flags, or_flags, exc_pos, &exc_n);
+    } else if (interior) {
+        for (int64_t idx = tid; idx < ntask; idx += kBlock)
+            tile_load_task<true>(k, idx, tile, ftile, want_flags, or_flags, exc_pos, &exc_n);
+    } else {
+        for (int64_t idx = tid; idx < ntask; idx += kBlock)
+            tile_load_task<false>(k, idx, tile, ftile, want_flags, or_flags, exc_pos, &exc_n);
+    }
+    __syncthreads();
+
+    // ---- TD exceptions: full composite map for the dwords that need it
+    if (k.n_td > 0) {
+        const uint32_t ne = exc_n;
+        if (ne <= (uint32_t)kExcCap) {
+            for (uint32_t e = tid; e < ne; e += kBlock) {
+                const uint32_t pos = exc_pos[e];
+                const int64_t c = pos >> 8;
+                const int w = pos & 255;
+                // the tile still holds this dword's raw bytes
+                uint32_t xv = 0;
+                for (int j = 0; j < 4; j++) xv |= (uint32_t)tile[(size_t)(4 * w + j) * k.Cp + c] << (8 * j);
+                uint32_t f;
+                put_dword_transposed(tile, k, c, w, td_map_dword(k, c, xv, &f));
+                if (want_flags) or_dword_transposed(ftile, k, c, w, f);
+            }
         } else {
-#pragma unroll
-            for (int j = 0; j < 4; j++) x[j] = (t + j < T) ? src[j] : 0;
-        }
-        if (seg.flags_mode == 2 && want_flags) {
-            const uint8_t* fs = bm.flags + c * stride + t;
-#pragma unroll
-            for (int j = 0; j < 4; j++) f[j] = (t + j < T) ? fs[j] : 0;
-        }
-        if (seg.n_td > 0) {
-            uint32_t r[kMaxSteps];
-            const uint32_t* rp = rec + (bm.row0 + c) * seg.n_td;
-            for (int j = 0; j < seg.n_td; j++) r[j] = rp[j];
-#pragma unroll
-            for (int j = 0; j < 4; j++) x[j] = td_map(x[j], r, seg.n_td, &f[j]);
-        }
-#pragma unroll
-        for (int j = 0; j < 4; j++) {
-            tile[(size_t)(4 * w + j) * Cp + c] = x[j];
-            if (want_flags) ftile[(size_t)(4 * w + j) * Cp + c] = f[j];
+            // worklist overflow: map every dword with an exception (the tile
+            // still holds raw bytes everywhere)
+            for (int64_t idx = tid; idx < ntask; idx += kBlock) {
+                const int64_t q4 = idx >> k.tw_log;
+                const int w = (int)(idx & (k.tw - 1));
+                const uint32_t valid = valid_bytes(k.t0 + 4 * w, k.T);
+                for (int i = 0; i < 4; i++) {
+                    const int64_t c = 4 * q4 + i;
+                    if (c >= k.C) continue;
+                    uint32_t xv = 0;
+                    for (int j = 0; j < 4; j++) xv |= (uint32_t)tile[(size_t)(4 * w + j) * k.Cp + c] << (8 * j);
+                    const uint32_t e = k.rec[c * k.n_td + (k.n_td - 1)];
+                    if (!(outside_mask(xv, klo_of(e & 255u), khi_of((e >> 8) & 255u)) & valid)) continue;
+                    uint32_t f;
+                    put_dword_transposed(tile, k, c, w, td_map_dword(k, c, xv, &f));
+                    if (want_flags) or_dword_transposed(ftile, k, c, w, f & valid);
+                }
+            }
         }
     }
     __syncthreads();
 
-    // ---- phase 2: FD steps; G consecutive lanes own one time sample
-    if (seg.n_fd > 0) {
-        const int G = kBlock / Tt;
-        const int tl = tid / G, q = tid % G;
-        const bool valid = t0 + tl < T;
-        uint8_t* colp = tile + (size_t)tl * Cp;
-        uint8_t* fcol = ftile + (size_t)tl * Cp;
-        for (int s = 0; s < seg.n_fd; s++) {
-            const SegStep& st = seg.fd[s];
-            const int64_t B = st.bin == 0 ? C : st.bin;
-            const int64_t nb = C / B;
-            // sum over bins of B * (B * Q_b - S_b^2) = sum over channels of Z_c^2
-            u128 sz2 = 0;
-            for (int64_t bb = q; bb < nb; bb += G) {
-                uint64_t S = 0, Q = 0;
-                const uint8_t* p = colp + bb * B;
-                for (int64_t i = 0; i < B; i++) {
-                    uint32_t x = p[i];
-                    S += x;
-                    Q += x * x;
-                }
-                sz2 += (u128)B * ((u128)B * Q - (u128)S * S);
-            }
-            sz2 = group_sum_u128(sz2, G);
-            const uint64_t z = fd_zthr(sz2, C, st.kx, (uint64_t)B * 255u);
-            uint64_t nflag = 0;
-            for (int64_t bb = q; bb < nb; bb += G) {
-                uint8_t* p = colp + bb * B;
-                uint64_t S = 0;
-                for (int64_t i = 0; i < B; i++) S += p[i];
-                int64_t lo = ceil_div((int64_t)S - (int64_t)z, B);
-                int64_t hi = floor_div((int64_t)S + (int64_t)z, B);
-                int64_t cnt = 0;
-                for (int64_t i = 0; i < B; i++) cnt += ((int64_t)p[i] < lo) || ((int64_t)p[i] > hi);
-                if (cnt == 0) continue;
-                const int r = st.replace == RFIM_REPLACE_MEDIAN ? lds_lower_median_u8(p, B, 1)
-                                                               : (int)rn_div_u64(S, (uint64_t)B);
-                for (int64_t i = 0; i < B; i++) {
-                    if (((int64_t)p[i] < lo) || ((int64_t)p[i] > hi)) {
-                        p[i] = (uint8_t)r;
-                        if (want_flags && st.bit >= 0) fcol[bb * B + i] |= (uint8_t)(1u << st.bit);
-                    }
-                }
-                nflag += (uint64_t)cnt;
-            }
-            if (valid && nflag && counts && st.bit >= 0) atomicAdd(&s_cnt[s], (unsigned long long)nflag);
-        }
-    }
+    // ---- phase 2: FD steps
+    if (seg.n_fd > 0) fd_steps<VEC>(k, seg, tile, ftile, want_flags, counts != nullptr, s_cnt);
     __syncthreads();
 
-    // ---- phase 3: write the tile back in row order
-    for (int64_t idx = tid; idx < C * tw; idx += kBlock) {
-        const int64_t c = idx / tw;
-        const int w = (int)(idx - c * tw);
-        const int64_t t = t0 + 4 * w;
-        uint8_t* dst = out + c * stride + t;
-        uint8_t x[4], f[4];
-#pragma unroll
-        for (int j = 0; j < 4; j++) {
-            x[j] = tile[(size_t)(4 * w + j) * Cp + c];
-            f[j] = want_flags ? ftile[(size_t)(4 * w + j) * Cp + c] : 0;
-        }
-        if (t + 3 < T && (((uintptr_t)dst) & 3) == 0) {
-            *(uint32_t*)dst = (uint32_t)x[0] | ((uint32_t)x[1] << 8) | ((uint32_t)x[2] << 16) |
-                              ((uint32_t)x[3] << 24);
-        } else {
-#pragma unroll
-            for (int j = 0; j < 4; j++)
-                if (t + j < T) dst[j] = x[j];
-        }
-        if (want_flags) {
-            uint8_t* fd = bm.flags + c * stride + t;
-#pragma unroll
-            for (int j = 0; j < 4; j++)
-                if (t + j < T) fd[j] = f[j];
-        }
+    // ---- phase 3: transposed back, rows out
+    if (wide) {
+        for (int64_t idx = tid; idx < ntask / 4; idx += kBlock) tile_store_task16(k, idx, tile, ftile, want_flags);
+    } else if (interior) {
+        for (int64_t idx = tid; idx < ntask; idx += kBlock) tile_store_task<true>(k, idx, tile, ftile, want_flags);
+    } else {
+        for (int64_t idx = tid; idx < ntask; idx += kBlock) tile_store_task<false>(k, idx, tile, ftile, want_flags);
     }
-    if (counts && seg.n_fd > 0) {
-        __syncthreads();
-        if (tid < seg.n_fd && s_cnt[tid] && seg.fd[tid].bit >= 0)
-            atomicAdd(&counts[(int64_t)bm.cidx * count_stride + seg.fd[tid].bit], s_cnt[tid]);
-    }
+    if (counts && seg.n_fd > 0 && tid < seg.n_fd && s_cnt[tid] && seg.fd[tid].bit >= 0)
+        atomicAdd(&counts[(int64_t)bm.cidx * count_stride + seg.fd[tid].bit], s_cnt[tid]);
 }
 
 hipError_t launch_td_rows_u8(const DevBeam* d_beams, int nbeams, int64_t total_rows,
                              const Segment& seg, uint32_t* d_rec, unsigned long long* d_counts,
                              int count_stride, hipStream_t s) {
     if (total_rows <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_td_rows_u8, dim3((unsigned)total_rows), dim3(kBlock), 0, s, d_beams,
-                       nbeams, seg, d_rec, d_counts, count_stride);
+    const int64_t wgs = (total_rows + kRowsPerWG - 1) / kRowsPerWG;
+    hipLaunchKernelGGL(k_td_rows_u8, dim3((unsigned)wgs), dim3(kBlock), 0, s, d_beams, nbeams,
+                       total_rows, seg, d_rec, d_counts, count_stride);
     return hipGetLastError();
 }
 
 hipError_t launch_fused_u8(const DevBeam* d_beams, int nbeams, int64_t total_tiles,
-                           const Segment& seg, const uint32_t* d_rec, size_t lds_bytes,
+                           const Segment& seg, const uint32_t* d_rec, size_t lds_bytes, bool vec,
                            unsigned long long* d_counts, int count_stride, hipStream_t s) {
     if (total_tiles <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_fused_u8, dim3((unsigned)total_tiles), dim3(kBlock), lds_bytes, s,
-                       d_beams, nbeams, total_tiles, seg, d_rec, d_counts, count_stride);
+    if (vec)
+        hipLaunchKernelGGL(k_fused_u8<true>, dim3((unsigned)total_tiles), dim3(kBlock), lds_bytes, s,
+                           d_beams, nbeams, total_tiles, seg, d_rec, d_counts, count_stride);
+    else
+        hipLaunchKernelGGL(k_fused_u8<false>, dim3((unsigned)total_tiles), dim3(kBlock), lds_bytes, s,
+                           d_beams, nbeams, total_tiles, seg, d_rec, d_counts, count_stride);
     return hipGetLastError();
 }
 
