@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <new>
@@ -141,6 +142,19 @@ std::vector<Segment> segments_of(const rfim_step* steps, int32_t nsteps) {
 }
 
 // Tile geometry of the fused kernel for one beam.
+// Largest fused-kernel tile width allowed (samples, power of two in [4, 64]);
+// RFIM_TILE_T in the environment caps it (tuning experiments).
+int tile_cap() {
+    static int cap = [] {
+        const char* e = std::getenv("RFIM_TILE_T");
+        int v = e ? std::atoi(e) : 64;
+        int p = 4;
+        while (p * 2 <= v && p < 64) p *= 2;
+        return p;
+    }();
+    return cap;
+}
+
 bool tile_shape(const rfim_beam& b, bool flags, int32_t* Tt, int32_t* Cp) {
     if (b.nchan >= ((int64_t)1 << 24)) return false;   // worklist packs the row in 24 bits
     // 16-byte aligned time samples (vector LDS reads), padded off a multiple
@@ -148,7 +162,7 @@ bool tile_shape(const rfim_beam& b, bool flags, int32_t* Tt, int32_t* Cp) {
     int64_t cp = ((b.nchan + 15) / 16) * 16;
     if (cp % 256 == 0 || cp % 256 == 128) cp += 16;
     size_t per = (size_t)cp * (flags ? 2 : 1);
-    int t = 64;
+    int t = tile_cap();
     while (t > 4 && per * t > kLdsBudget) t >>= 1;
     if (per * t > kLdsMax) return false;
     *Tt = t;

@@ -105,6 +105,23 @@ __device__ inline bool le_k2(u128 A, u128 V, const KExact& kx) {
     return le_k2_wide(A, V, kx);
 }
 
+// A <= k^2 * V when both sides fit 64 bits (the usual case for small k
+// mantissas); otherwise the 128/512-bit comparison.
+__device__ inline bool le_k2_small(uint64_t A, uint64_t V, const KExact& kx) {
+    if (kx.mode == 0 && kx.mk2_hi == 0) {
+        const int la = A ? 64 - __clzll((long long)A) : 0;
+        const int lv = V ? 64 - __clzll((long long)V) : 0;
+        if (kx.ek <= 0) {
+            const int s = -2 * kx.ek;
+            if (la + s <= 63 && kx.mk2_bits + lv <= 63) return (A << s) <= kx.mk2_lo * V;
+        } else {
+            const int s = 2 * kx.ek;
+            if (kx.mk2_bits + lv + s <= 63) return A <= ((kx.mk2_lo * V) << s);
+        }
+    }
+    return le_k2((u128)A, (u128)V, kx);
+}
+
 // num / den rounded to nearest, ties to even (den > 0, den < 2^62)
 __device__ inline uint64_t rn_div_u64(uint64_t num, uint64_t den) {
     uint64_t q = num / den, r = num - q * den;
@@ -139,6 +156,17 @@ __device__ inline uint64_t fd_zthr(u128 SZ2, int64_t C, const KExact& kx, uint64
     double e = kx.mode == 0 ? floor(kx.k * sqrt((double)SZ2 / (double)C))
                             : (kx.mode == 2 ? (double)zcap : 0.0);
     uint64_t z = e >= (double)zcap ? zcap : (e < 0.0 ? 0 : (uint64_t)e);
+    while (z < zcap && ok(z + 1)) z++;
+    while (z > 0 && !ok(z)) z--;
+    return z;
+}
+
+// fd_zthr for sums that fit 64 bits: the largest z in [0, zcap] with
+// C*z^2 <= k^2 * SZ2 (zcap < 2^24, C < 2^31)
+__device__ inline uint32_t fd_zthr_small(uint64_t SZ2, uint32_t C, const KExact& kx, uint32_t zcap) {
+    auto ok = [&](uint32_t z) -> bool { return le_k2_small((uint64_t)C * ((uint64_t)z * z), SZ2, kx); };
+    double e = kx.mode == 0 ? floor(kx.k * sqrt((double)SZ2 / (double)C)) : (kx.mode == 2 ? (double)zcap : 0.0);
+    uint32_t z = e >= (double)zcap ? zcap : (e < 0.0 ? 0u : (uint32_t)e);
     while (z < zcap && ok(z + 1)) z++;
     while (z > 0 && !ok(z)) z--;
     return z;

@@ -157,67 +157,60 @@ __device__ inline void hist4(uint32_t* h, uint32_t v) {
 
 }  // namespace
 
-__global__ __launch_bounds__(kBlock) void k_td_rows_u8(const DevBeam* __restrict__ beams,
-                                                       int nbeams, int64_t total_rows, Segment seg,
-                                                       uint32_t* __restrict__ rec,
-                                                       unsigned long long* __restrict__ counts,
-                                                       int count_stride) {
-    __shared__ uint32_t hist_all[kRowsPerWG][kHistCopies * kHistPitch];
-    __shared__ int s_lo_all[kRowsPerWG][kMaxSteps], s_hi_all[kRowsPerWG][kMaxSteps],
-        s_r_all[kRowsPerWG][kMaxSteps];
-
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int64_t g = (int64_t)blockIdx.x * kRowsPerWG + wave;
-    if (g >= total_rows) return;
-    uint32_t* hist = hist_all[wave];
-    int* s_lo = s_lo_all[wave];
-    int* s_hi = s_hi_all[wave];
-    int* s_r = s_r_all[wave];
-    const int b = find_beam_by_row(beams, nbeams, g);
-    const DevBeam& bm = beams[b];
-    const int64_t c = g - bm.row0;
-    const int64_t T = bm.T;
-    const uint8_t* row = (const uint8_t*)bm.in + c * bm.stride;
-
-    for (int i = lane; i < kHistCopies * kHistPitch; i += 64) hist[i] = 0;
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-
-    // histogram: bytes up to a dword boundary, then 16-byte loads (dword
-    // aligned), then the tail bytes
-    uint32_t* h = hist + (lane & 3) * kHistPitch;
+// One pass over a row by one wave: dword-aligned 16-byte loads for the bulk,
+// single bytes for the unaligned head and the tail.
+template <typename FD, typename FB>
+__device__ inline void row_pass(const uint8_t* row, int64_t T, int lane, FD&& on_dword, FB&& on_byte) {
     int64_t head = (int64_t)((4 - ((uintptr_t)row & 3)) & 3);
     if (head > T) head = T;
-    if (lane < head) atomicAdd(&h[row[lane]], 1u);
+    if (lane < head) on_byte((uint32_t)row[lane]);
     const int64_t n16 = (T - head) >> 4;
     const uint8_t* body = row + head;
     int64_t i = lane;
     for (; i + 64 < n16; i += 128) {
         const uint4 v0 = *(const uint4*)(body + 16 * i);
         const uint4 v1 = *(const uint4*)(body + 16 * (i + 64));
-        hist4(h, v0.x); hist4(h, v0.y); hist4(h, v0.z); hist4(h, v0.w);
-        hist4(h, v1.x); hist4(h, v1.y); hist4(h, v1.z); hist4(h, v1.w);
+        on_dword(v0.x); on_dword(v0.y); on_dword(v0.z); on_dword(v0.w);
+        on_dword(v1.x); on_dword(v1.y); on_dword(v1.z); on_dword(v1.w);
     }
     for (; i < n16; i += 64) {
         const uint4 v0 = *(const uint4*)(body + 16 * i);
-        hist4(h, v0.x); hist4(h, v0.y); hist4(h, v0.z); hist4(h, v0.w);
+        on_dword(v0.x); on_dword(v0.y); on_dword(v0.z); on_dword(v0.w);
     }
-    for (int64_t k = head + 16 * n16 + lane; k < T; k += 64) atomicAdd(&h[row[k]], 1u);
-    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-    __builtin_amdgcn_wave_barrier();
+    for (int64_t k = head + 16 * n16 + lane; k < T; k += 64) on_byte((uint32_t)row[k]);
+}
 
-    // lane l owns the byte values 4l .. 4l+3
-    uint32_t hv[4];
-#pragma unroll
+// Exact TD test of the byte values 4*lane .. 4*lane+3: bit u of the result is
+// set when value 4*lane+u is kept; *lo, *hi = the kept interval over all 256
+// values (wave-uniform; *lo > *hi when empty).
+__device__ inline uint32_t td_keep_interval(uint64_t n, uint64_t S1, u128 D, const KExact& kx, int lane,
+                                            int* lo, int* hi) {
+    uint32_t bits = 0;
+    int l = 256, h = -1;
+#pragma unroll 1
     for (int u = 0; u < 4; u++) {
-        const int v = 4 * lane + u;
-        uint32_t t = 0;
-#pragma unroll
-        for (int cp = 0; cp < kHistCopies; cp++) t += hist[cp * kHistPitch + v];
-        hv[u] = t;
+        const bool kp = td_keeps_u8(n, S1, D, 4 * lane + u, kx);
+        bits |= (kp ? 1u : 0u) << u;
+        const uint64_t km = __ballot(kp);
+        if (km) {
+            l = min(l, 4 * (__ffsll((unsigned long long)km) - 1) + u);
+            h = max(h, 4 * (63 - __clzll((long long)km)) + u);
+        }
     }
-    const uint64_t n = (uint64_t)T;
+    *lo = l;
+    *hi = h;
+    return bits;
+}
 
+// Runs every TD step of the run for one row (one wave).  The row is described
+// by hv[u] = number of samples with byte value 4*lane+u among the tracked
+// values, plus an aggregate (nJ samples, sums S1J, S2J) of untracked values
+// that all lie in [jlo, jhi].  Untracked values are never cut as long as every
+// step keeps [jlo, jhi]; if a step does not, returns false and writes nothing
+// (the caller retries with every value tracked).  Median steps need nJ == 0.
+__device__ bool td_decide(const Segment& seg, uint64_t n, uint32_t hv[4], uint64_t nJ, uint64_t S1J,
+                          uint64_t S2J, int jlo, int jhi, int lane, int* s_lo, int* s_hi, int* s_r,
+                          unsigned long long* s_mv, unsigned long long* cnt_row) {
     for (int j = 0; j < seg.n_td; j++) {
         const SegStep& st = seg.td[j];
         uint64_t S1 = 0, S2 = 0;
@@ -227,8 +220,8 @@ __global__ __launch_bounds__(kBlock) void k_td_rows_u8(const DevBeam* __restrict
             S1 += (uint64_t)hv[u] * v;
             S2 += (uint64_t)hv[u] * v * v;
         }
-        S1 = wave_sum_u64_split(S1);   // below 2^39 for n < 2^31
-        S2 = wave_sum_u64_split(S2);   // below 2^47 for n < 2^31
+        S1 = wave_sum_u64_split(S1) + S1J;   // below 2^39 / 2^47 for n < 2^31
+        S2 = wave_sum_u64_split(S2) + S2J;
         int r;
         if (st.replace == RFIM_REPLACE_MEDIAN) {
             // lower median: the byte value holding rank floor((n-1)/2)
@@ -254,33 +247,95 @@ __global__ __launch_bounds__(kBlock) void k_td_rows_u8(const DevBeam* __restrict
         }
         // every byte value is tested exactly
         const u128 D = (u128)n * S2 - (u128)S1 * S1;
-        bool keep[4];
-        int lo = 256, hi = -1;
-#pragma unroll
-        for (int u = 0; u < 4; u++) {
-            keep[u] = td_keeps_u8(n, S1, D, 4 * lane + u, st.kx);
-            const uint64_t km = __ballot(keep[u]);
-            if (km) {
-                lo = min(lo, 4 * (__ffsll((unsigned long long)km) - 1) + u);
-                hi = max(hi, 4 * (63 - __clzll((long long)km)) + u);
-            }
-        }
+        int lo, hi;
+        const uint32_t keepbits = td_keep_interval(n, S1, D, st.kx, lane, &lo, &hi);
+        if (nJ > 0 && (lo > jlo || hi < jhi)) return false;   // an untracked value may be cut
         uint32_t moved32 = 0;
 #pragma unroll
-        for (int u = 0; u < 4; u++) moved32 += keep[u] ? 0u : hv[u];
+        for (int u = 0; u < 4; u++) moved32 += ((keepbits >> u) & 1) ? 0u : hv[u];
         const uint64_t moved = wave_sum_u32(moved32);   // at most n < 2^31
 #pragma unroll
-        for (int u = 0; u < 4; u++) {
-            if (!keep[u]) hv[u] = 0;
-            if (4 * lane + u == r) hv[u] += (uint32_t)moved;
+        for (int u = 0; u < 4; u++) if (!((keepbits >> u) & 1)) hv[u] = 0;
+        if (nJ > 0 && r >= jlo && r <= jhi) {
+            nJ += moved;
+            S1J += moved * (uint64_t)r;
+            S2J += moved * (uint64_t)r * (uint64_t)r;
+        } else {
+#pragma unroll
+            for (int u = 0; u < 4; u++) if (4 * lane + u == r) hv[u] += (uint32_t)moved;
         }
         if (lane == 0) {
             s_lo[j] = lo <= hi ? lo : 1;   // kept values form [lo, hi]; empty as [1, 0]
             s_hi[j] = lo <= hi ? hi : 0;
             s_r[j] = r;
-            if (counts && st.bit >= 0 && moved)
-                atomicAdd(&counts[(int64_t)bm.cidx * count_stride + st.bit], (unsigned long long)moved);
+            s_mv[j] = moved;
         }
+    }
+    if (cnt_row && lane == 0)
+        for (int j = 0; j < seg.n_td; j++)
+            if (seg.td[j].bit >= 0 && s_mv[j]) atomicAdd(&cnt_row[seg.td[j].bit], s_mv[j]);
+    return true;
+}
+
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) void k_td_rows_u8(const DevBeam* __restrict__ beams,
+                                                       int nbeams, int64_t total_rows, Segment seg,
+                                                       uint32_t* __restrict__ rec,
+                                                       unsigned long long* __restrict__ counts,
+                                                       int count_stride) {
+    __shared__ uint32_t hist_all[kRowsPerWG][kHistCopies * kHistPitch];
+    __shared__ int s_lo_all[kRowsPerWG][kMaxSteps], s_hi_all[kRowsPerWG][kMaxSteps],
+        s_r_all[kRowsPerWG][kMaxSteps];
+    __shared__ unsigned long long s_mv_all[kRowsPerWG][kMaxSteps];
+
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t g = (int64_t)blockIdx.x * kRowsPerWG + wave;
+    if (g >= total_rows) return;
+    unsigned long long* s_mv = s_mv_all[wave];
+    uint32_t* hist = hist_all[wave];
+    int* s_lo = s_lo_all[wave];
+    int* s_hi = s_hi_all[wave];
+    int* s_r = s_r_all[wave];
+    const int b = find_beam_by_row(beams, nbeams, g);
+    const DevBeam& bm = beams[b];
+    const int64_t c = g - bm.row0;
+    const int64_t T = bm.T;
+    const uint64_t n = (uint64_t)T;
+    const uint8_t* row = (const uint8_t*)bm.in + c * bm.stride;
+    unsigned long long* cnt_row = counts ? counts + (int64_t)bm.cidx * count_stride : nullptr;
+    uint32_t* h = hist + (lane & (kHistCopies - 1)) * kHistPitch;
+    bool median = false;
+    for (int j = 0; j < seg.n_td; j++) median |= seg.td[j].replace == RFIM_REPLACE_MEDIAN;
+
+    auto clear_hist = [&] {
+        for (int i = lane; i < kHistCopies * kHistPitch; i += 64) hist[i] = 0;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+    };
+    // lane l owns the byte values 4l .. 4l+3
+    auto read_hist = [&](uint32_t hv[4]) {
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            uint32_t t = 0;
+#pragma unroll
+            for (int cp = 0; cp < kHistCopies; cp++) t += hist[cp * kHistPitch + 4 * lane + u];
+            hv[u] = t;
+        }
+    };
+
+    // A two-pass form (exact S1, S2 by dot4, then a histogram of the samples
+    // outside the middle of the first cut only) costs a second read of the row
+    // from L2/MALL, which measures slower than one pass with a full histogram.
+    bool done = false;
+    (void)median;
+    if (!done) {
+        // every value tracked: the row's full histogram
+        clear_hist();
+        row_pass(row, T, lane, [&](uint32_t x) { hist4(h, x); }, [&](uint32_t x) { atomicAdd(&h[x], 1u); });
+        uint32_t hv[4];
+        read_hist(hv);
+        td_decide(seg, n, hv, 0, 0, 0, 1, 0, lane, s_lo, s_hi, s_r, s_mv, cnt_row);
     }
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -427,6 +482,20 @@ __device__ inline uint32_t valid_bytes(int64_t t, int64_t T) {
     return t + 3 < T ? 0xFFFFFFFFu : (t >= T ? 0u : (0xFFFFFFFFu >> (8 * (4 - (T - t)))));
 }
 
+// TD composite map of one dword of row c (4 samples) in registers; *fv gets
+// the flag bytes.  Used when the exception worklist is full.
+__device__ inline uint32_t td_map_regs(const TileCtx& k, int64_t c, uint32_t xv, uint32_t* fv) {
+    const uint32_t* rp = k.rec + c * k.n_td;
+    uint32_t nv = 0, f4 = 0;
+    for (int j = 0; j < 4; j++) {
+        uint32_t f;
+        nv |= td_map_byte((xv >> (8 * j)) & 255u, rp, k.n_td, &f) << (8 * j);
+        f4 |= f << (8 * j);
+    }
+    *fv = f4;
+    return nv;
+}
+
 // Phase 1 body for one row-quad task: 4 rows in, TD fast check (exceptions
 // to the worklist), 4x4 transpose, LDS tile [Tt][Cp]
 template <bool INTERIOR>
@@ -436,7 +505,7 @@ __device__ inline void tile_load_task(const TileCtx& k, int64_t idx, uint8_t* ti
     const int64_t q4 = idx >> k.tw_log;
     const int w = (int)(idx & (k.tw - 1));
     const int64_t c0 = 4 * q4;
-    uint32_t x[4], y[4];
+    uint32_t x[4], y[4], tf[4] = {0u, 0u, 0u, 0u};
     load_quad<INTERIOR>(k, k.in, c0, w, x);
     if (k.n_td > 0) {
         const uint32_t valid = INTERIOR ? 0xFFFFFFFFu : valid_bytes(k.t0 + 4 * w, k.T);
@@ -448,7 +517,12 @@ __device__ inline void tile_load_task(const TileCtx& k, int64_t idx, uint8_t* ti
             if (c0 + i >= k.C) m = 0;
             if (m) {
                 const uint32_t slot = atomicAdd(exc_n, 1u);
-                if (slot < (uint32_t)kExcCap) exc_pos[slot] = ((uint32_t)(c0 + i) << 8) | (uint32_t)w;
+                if (slot < (uint32_t)kExcCap) {
+                    exc_pos[slot] = ((uint32_t)(c0 + i) << 8) | (uint32_t)w;
+                } else {   // worklist full: map here
+                    x[i] = td_map_regs(k, c, x[i], &tf[i]);
+                    tf[i] &= valid;
+                }
             }
         }
     }
@@ -458,6 +532,8 @@ __device__ inline void tile_load_task(const TileCtx& k, int64_t idx, uint8_t* ti
     if (want_flags) {
         uint32_t fx[4] = {0u, 0u, 0u, 0u}, fy[4];
         if (or_flags) load_quad<INTERIOR>(k, k.flags, c0, w, fx);
+#pragma unroll
+        for (int i = 0; i < 4; i++) fx[i] |= tf[i];
         transpose4(fx, fy);
 #pragma unroll
         for (int j = 0; j < 4; j++) *(uint32_t*)(ftile + (size_t)(4 * w + j) * k.Cp + c0) = fy[j];
@@ -480,14 +556,16 @@ __device__ inline void tile_load_task16(const TileCtx& k, int64_t idx, uint8_t* 
         x[i] = *(const uint4*)(k.in + c * k.stride + k.t0 + 16 * w16);
         if (c0 + i >= k.C) x[i] = make_uint4(0u, 0u, 0u, 0u);
     }
+    uint32_t tf[4][4] = {};   // TD flag bytes of dwords mapped here (worklist full)
     if (k.n_td > 0) {
 #pragma unroll
         for (int i = 0; i < 4; i++) {
             if (c0 + i >= k.C) continue;
             const uint32_t e = k.rec[(c0 + i) * k.n_td + (k.n_td - 1)];
             const uint32_t klo = klo_of(e & 255u), khi = khi_of((e >> 8) & 255u);
-            const uint32_t m0 = outside_mask(x[i].x, klo, khi), m1 = outside_mask(x[i].y, klo, khi);
-            const uint32_t m2 = outside_mask(x[i].z, klo, khi), m3 = outside_mask(x[i].w, klo, khi);
+            uint32_t* xi = &x[i].x;
+            const uint32_t m0 = outside_mask(xi[0], klo, khi), m1 = outside_mask(xi[1], klo, khi);
+            const uint32_t m2 = outside_mask(xi[2], klo, khi), m3 = outside_mask(xi[3], klo, khi);
             if (m0 | m1 | m2 | m3) {
                 const uint32_t mm[4] = {m0, m1, m2, m3};
 #pragma unroll
@@ -496,6 +574,8 @@ __device__ inline void tile_load_task16(const TileCtx& k, int64_t idx, uint8_t* 
                     const uint32_t slot = atomicAdd(exc_n, 1u);
                     if (slot < (uint32_t)kExcCap)
                         exc_pos[slot] = ((uint32_t)(c0 + i) << 8) | (uint32_t)(4 * w16 + j);
+                    else   // worklist full: map here
+                        xi[j] = td_map_regs(k, c0 + i, xi[j], &tf[i][j]);
                 }
             }
         }
@@ -512,6 +592,7 @@ __device__ inline void tile_load_task16(const TileCtx& k, int64_t idx, uint8_t* 
         for (int j = 0; j < 4; j++) {
             uint32_t fx[4] = {0u, 0u, 0u, 0u}, fy[4];
             if (or_flags) load_quad<true>(k, k.flags, c0, 4 * w16 + j, fx);
+            for (int i = 0; i < 4; i++) fx[i] |= tf[i][j];
             transpose4(fx, fy);
             for (int jj = 0; jj < 4; jj++)
                 *(uint32_t*)(ftile + (size_t)(16 * w16 + 4 * j + jj) * k.Cp + c0) = fy[jj];
@@ -755,6 +836,128 @@ __device__ inline void fd_steps(const TileCtx& k, const Segment& seg, uint8_t* t
     }
 }
 
+// Sum over groups of G consecutive lanes (G = 4, 8 or 16) with DPP: quad
+// swaps, then the half-row and row mirrors; every lane gets its group's sum.
+template <int G>
+__device__ inline uint32_t group_sum_dpp(uint32_t v) {
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xf, 0xf, false);    // quad_perm 1,0,3,2
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xf, 0xf, false);    // quad_perm 2,3,0,1
+    if (G >= 8) v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x141, 0xf, 0xf, false);  // row_half_mirror
+    if (G >= 16) v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x140, 0xf, 0xf, false); // row_mirror
+    return v;
+}
+
+constexpr int kB32MaxBins = 7;   // bins per lane in the 32-channel path (LDS budget bound)
+
+// FD steps for bins of 32 channels: G lanes per time sample, lane q owns bins
+// q, q+G, ... (at most kB32MaxBins).  Per bin: S = sum x <= 8160 and
+// Q = sum x^2 <= 2.1e6, and sum over the bin of Z^2 = 32*(32*Q - S^2) < 2^30,
+// so everything is 32-bit until the column total.
+template <int G>
+__device__ inline void fd_steps_b32(const TileCtx& k, const Segment& seg, uint8_t* tile, uint8_t* ftile,
+                                    bool want_flags, bool count, unsigned long long* s_cnt) {
+    const int tid = threadIdx.x;
+    const int tl = tid / G, q = tid % G;
+    const bool valid = k.t0 + tl < k.T;
+    const uint32_t C = (uint32_t)k.C;
+    const int nb = (int)(C >> 5);
+    const uint32_t col = (uint32_t)tl * (uint32_t)k.Cp;
+    for (int s = 0; s < seg.n_fd; s++) {
+        const SegStep& st = seg.fd[s];
+        uint32_t Sb[kB32MaxBins];
+        uint32_t zlo = 0, zhi = 0;   // per-lane sum of Z^2 as 24-bit slices
+#pragma unroll
+        for (int i = 0; i < kB32MaxBins; i++) {
+            const int bb = q + i * G;
+            Sb[i] = 0;
+            if (bb < nb) {
+                const uint32_t off = col + (uint32_t)bb * 32u;
+                const uint4 a = *(const uint4*)(tile + off);
+                const uint4 b = *(const uint4*)(tile + off + 16);
+                uint32_t S = __builtin_amdgcn_udot4(a.x, 0x01010101u, 0u, false);
+                S = __builtin_amdgcn_udot4(a.y, 0x01010101u, S, false);
+                S = __builtin_amdgcn_udot4(a.z, 0x01010101u, S, false);
+                S = __builtin_amdgcn_udot4(a.w, 0x01010101u, S, false);
+                S = __builtin_amdgcn_udot4(b.x, 0x01010101u, S, false);
+                S = __builtin_amdgcn_udot4(b.y, 0x01010101u, S, false);
+                S = __builtin_amdgcn_udot4(b.z, 0x01010101u, S, false);
+                S = __builtin_amdgcn_udot4(b.w, 0x01010101u, S, false);
+                uint32_t Q = __builtin_amdgcn_udot4(a.x, a.x, 0u, false);
+                Q = __builtin_amdgcn_udot4(a.y, a.y, Q, false);
+                Q = __builtin_amdgcn_udot4(a.z, a.z, Q, false);
+                Q = __builtin_amdgcn_udot4(a.w, a.w, Q, false);
+                Q = __builtin_amdgcn_udot4(b.x, b.x, Q, false);
+                Q = __builtin_amdgcn_udot4(b.y, b.y, Q, false);
+                Q = __builtin_amdgcn_udot4(b.z, b.z, Q, false);
+                Q = __builtin_amdgcn_udot4(b.w, b.w, Q, false);
+                Sb[i] = S;
+                const uint32_t zb = 32u * (32u * Q - S * S);
+                zlo += zb & 0xFFFFFFu;
+                zhi += zb >> 24;
+            }
+        }
+        zlo = group_sum_dpp<G>(zlo);
+        zhi = group_sum_dpp<G>(zhi);
+        const uint64_t sz2 = (uint64_t)zlo + ((uint64_t)zhi << 24);
+        const uint32_t z = fd_zthr_small(sz2, C, st.kx, 32u * 255u);
+        const uint32_t fbit = st.bit >= 0 ? (1u << st.bit) * 0x01010101u : 0u;
+        uint32_t nflag = 0;
+#pragma unroll
+        for (int i = 0; i < kB32MaxBins; i++) {
+            const int bb = q + i * G;
+            if (bb >= nb) continue;
+            const uint32_t S = Sb[i];
+            // kept: |32 x - S| <= z  <=>  ceil((S - z)/32) <= x <= floor((S + z)/32)
+            const int lo = -(((int)z - (int)S) >> 5);
+            const int hi = (int)((S + z) >> 5);
+            const int lc = lo < 0 ? 0 : lo, hc = hi > 255 ? 255 : hi;
+            uint32_t klo = klo_of(1), khi = khi_of(0);   // empty interval
+            if (lc <= hc) {
+                klo = klo_of((uint32_t)lc);
+                khi = khi_of((uint32_t)hc);
+            }
+            const uint32_t off = col + (uint32_t)bb * 32u;
+            uint4 a = *(const uint4*)(tile + off);
+            uint4 b = *(const uint4*)(tile + off + 16);
+            const uint32_t m0 = outside_mask(a.x, klo, khi), m1 = outside_mask(a.y, klo, khi);
+            const uint32_t m2 = outside_mask(a.z, klo, khi), m3 = outside_mask(a.w, klo, khi);
+            const uint32_t m4 = outside_mask(b.x, klo, khi), m5 = outside_mask(b.y, klo, khi);
+            const uint32_t m6 = outside_mask(b.z, klo, khi), m7 = outside_mask(b.w, klo, khi);
+            if (m0 | m1 | m2 | m3 | m4 | m5 | m6 | m7) {
+                uint32_t r;
+                if (st.replace == RFIM_REPLACE_MEDIAN) {
+                    r = lds_lower_median_u8(tile + off, 32);
+                } else {
+                    const uint32_t qv = S >> 5, rem = S & 31u;
+                    r = qv + ((rem > 16u || (rem == 16u && (qv & 1u))) ? 1u : 0u);
+                }
+                const uint32_t rr = r * 0x01010101u;
+                a.x = (a.x & ~m0) | (rr & m0);
+                a.y = (a.y & ~m1) | (rr & m1);
+                a.z = (a.z & ~m2) | (rr & m2);
+                a.w = (a.w & ~m3) | (rr & m3);
+                b.x = (b.x & ~m4) | (rr & m4);
+                b.y = (b.y & ~m5) | (rr & m5);
+                b.z = (b.z & ~m6) | (rr & m6);
+                b.w = (b.w & ~m7) | (rr & m7);
+                *(uint4*)(tile + off) = a;
+                *(uint4*)(tile + off + 16) = b;
+                if (want_flags) {
+                    uint4 fa = *(const uint4*)(ftile + off);
+                    uint4 fb = *(const uint4*)(ftile + off + 16);
+                    fa.x |= m0 & fbit; fa.y |= m1 & fbit; fa.z |= m2 & fbit; fa.w |= m3 & fbit;
+                    fb.x |= m4 & fbit; fb.y |= m5 & fbit; fb.z |= m6 & fbit; fb.w |= m7 & fbit;
+                    *(uint4*)(ftile + off) = fa;
+                    *(uint4*)(ftile + off + 16) = fb;
+                }
+                nflag += (uint32_t)(__popc(m0) + __popc(m1) + __popc(m2) + __popc(m3) + __popc(m4) +
+                                    __popc(m5) + __popc(m6) + __popc(m7)) >> 3;
+            }
+        }
+        if (valid && nflag && count && st.bit >= 0) atomicAdd(&s_cnt[s], (unsigned long long)nflag);
+    }
+}
+
 // One work-group per (beam, time tile); work-groups are handed out so that
 // each XCD gets a contiguous range of tiles.
 template <bool VEC>
@@ -816,44 +1019,36 @@ __global__ __launch_bounds__(kBlock) void k_fused_u8(const DevBeam* __restrict__
 
     // ---- TD exceptions: full composite map for the dwords that need it
     if (k.n_td > 0) {
-        const uint32_t ne = exc_n;
-        if (ne <= (uint32_t)kExcCap) {
-            for (uint32_t e = tid; e < ne; e += kBlock) {
-                const uint32_t pos = exc_pos[e];
-                const int64_t c = pos >> 8;
-                const int w = pos & 255;
-                // the tile still holds this dword's raw bytes
-                uint32_t xv = 0;
-                for (int j = 0; j < 4; j++) xv |= (uint32_t)tile[(size_t)(4 * w + j) * k.Cp + c] << (8 * j);
-                uint32_t f;
-                put_dword_transposed(tile, k, c, w, td_map_dword(k, c, xv, &f));
-                if (want_flags) or_dword_transposed(ftile, k, c, w, f);
-            }
-        } else {
-            // worklist overflow: map every dword with an exception (the tile
-            // still holds raw bytes everywhere)
-            for (int64_t idx = tid; idx < ntask; idx += kBlock) {
-                const int64_t q4 = idx >> k.tw_log;
-                const int w = (int)(idx & (k.tw - 1));
-                const uint32_t valid = valid_bytes(k.t0 + 4 * w, k.T);
-                for (int i = 0; i < 4; i++) {
-                    const int64_t c = 4 * q4 + i;
-                    if (c >= k.C) continue;
-                    uint32_t xv = 0;
-                    for (int j = 0; j < 4; j++) xv |= (uint32_t)tile[(size_t)(4 * w + j) * k.Cp + c] << (8 * j);
-                    const uint32_t e = k.rec[c * k.n_td + (k.n_td - 1)];
-                    if (!(outside_mask(xv, klo_of(e & 255u), khi_of((e >> 8) & 255u)) & valid)) continue;
-                    uint32_t f;
-                    put_dword_transposed(tile, k, c, w, td_map_dword(k, c, xv, &f));
-                    if (want_flags) or_dword_transposed(ftile, k, c, w, f & valid);
-                }
-            }
+        const uint32_t ne = min(exc_n, (uint32_t)kExcCap);   // the rest were mapped in phase 1
+        for (uint32_t e = tid; e < ne; e += kBlock) {
+            const uint32_t pos = exc_pos[e];
+            const int64_t c = pos >> 8;
+            const int w = pos & 255;
+            // the tile still holds this dword's raw bytes
+            uint32_t xv = 0;
+            for (int j = 0; j < 4; j++) xv |= (uint32_t)tile[(size_t)(4 * w + j) * k.Cp + c] << (8 * j);
+            uint32_t f;
+            put_dword_transposed(tile, k, c, w, td_map_dword(k, c, xv, &f));
+            if (want_flags) or_dword_transposed(ftile, k, c, w, f);
         }
     }
     __syncthreads();
 
     // ---- phase 2: FD steps
-    if (seg.n_fd > 0) fd_steps<VEC>(k, seg, tile, ftile, want_flags, counts != nullptr, s_cnt);
+    if (seg.n_fd > 0) {
+        // 32-channel bins with every lane's bins whole: the specialised path
+        bool b32 = VEC && (k.C & 31) == 0 && (k.C >> 5) <= kB32MaxBins * (kBlock / k.Tt);
+        for (int s = 0; s < seg.n_fd; s++) b32 &= seg.fd[s].bin == 32 || (seg.fd[s].bin == 0 && k.C == 32);
+        const bool cnt = counts != nullptr;
+        if (b32 && k.Tt == 32)
+            fd_steps_b32<8>(k, seg, tile, ftile, want_flags, cnt, s_cnt);
+        else if (b32 && k.Tt == 16)
+            fd_steps_b32<16>(k, seg, tile, ftile, want_flags, cnt, s_cnt);
+        else if (b32 && k.Tt == 64)
+            fd_steps_b32<4>(k, seg, tile, ftile, want_flags, cnt, s_cnt);
+        else
+            fd_steps<VEC>(k, seg, tile, ftile, want_flags, cnt, s_cnt);
+    }
     __syncthreads();
 
     // ---- phase 3: transposed back, rows out

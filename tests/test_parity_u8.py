@@ -176,6 +176,23 @@ def test_edge_cases(rf, case):
     check_against_oracle([x], steps, out, fl)
 
 
+@pytest.mark.parametrize("frac", [0.0, 0.001, 0.02, 0.1, 0.3])
+def test_td_iterations_with_shrinking_spread(rf, frac):
+    """Rows whose spread collapses after the first cut (a fraction of samples
+    at 255 over a narrow background): later TD steps cut deep inside the first
+    step's interval, which the kernel must handle exactly."""
+    rng = np.random.default_rng(int(frac * 1000) + 3)
+    x = rng.normal(40, 3, size=(64, 12500)).clip(0, 255)
+    hit = rng.random(x.shape) < frac
+    x[hit] = 255
+    x[::7, :] = rng.normal(90, 20, size=(10, 12500)).clip(0, 255)   # some plain wide rows
+    x = x.astype(np.uint8)
+    steps = [synth.td(4.0), synth.td(3.5), synth.td(3.25), synth.td(2.0), synth.fd(2.75, 32)]
+    say(f"shrinking spread frac={frac}")
+    out, fl, counts = gpu_run(rf, [x], steps, plan=True)
+    check_against_oracle([x], steps, out, fl, counts=counts)
+
+
 def test_td_and_fd_entry_points(rf):
     """rfim_td_sigma_cut and rfim_fd_sigma_cut are the one-step pipelines."""
     import torch
