@@ -20,10 +20,96 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+PROFILES = os.path.join(ROOT, "profiles")
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def source_hash() -> str:
+    """Hash of the HIP sources: a traffic measurement is valid only for the
+    kernels it was taken on."""
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    files = sorted(glob.glob(os.path.join(ROOT, "paper_2001_03389_amd", "csrc", "*")))
+    files.append(os.path.join(ROOT, "include", "rfim.h"))
+    for f in files:
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic(kernel: str, workload: str):
+    """Measured HBM bytes per launch from profiles/traffic_<kernel>_<workload>.txt
+    (rocprofv3 FETCH_SIZE / WRITE_SIZE, scaled by a plain copy of known size),
+    or None when missing or taken on other kernel sources."""
+    path = os.path.join(PROFILES, f"traffic_{kernel}_{workload}.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if "=" in line and not line.startswith("#"):
+            a, b = line.split("=", 1)
+            kv[a.strip()] = b.strip()
+    if kv.get("src_hash") != source_hash():
+        return None
+    return int(float(kv["traffic_bytes_per_launch"]))
+
+
+def summarize(stats_csv, fetch_csv, write_csv, command, workload):
+    """Writes profiles/ summaries from rocprofv3 CSV output (kernel stats, and
+    FETCH_SIZE / WRITE_SIZE counter runs that include one plain device copy of
+    the batch size as calibration)."""
+    import csv
+    os.makedirs(PROFILES, exist_ok=True)
+    rows = list(csv.DictReader(open(stats_csv)))
+    lines = [f"# rocprofv3 kernel statistics, workload {workload}", "",
+             f"command: {command}", f"kernel sources: {source_hash()}", "",
+             "| kernel | calls | average ms | min ms | max ms | share % |", "|---|---|---|---|---|---|"]
+    for r in rows:
+        lines.append(f"| {r['Name'].split('(')[0]} | {r['Calls']} | {float(r['AverageNs'])/1e6:.4f} | "
+                     f"{float(r['MinNs'])/1e6:.4f} | {float(r['MaxNs'])/1e6:.4f} | {float(r['Percentage']):.2f} |")
+    with open(os.path.join(PROFILES, f"kernel_stats_{workload}.md"), "w") as f:
+        f.write("\n".join(lines) + "\n")
+
+    def per_kernel(path, counter):
+        out = {}
+        copy = None
+        for r in csv.DictReader(open(path)):
+            if r["Counter_Name"] != counter:
+                continue
+            name = r["Kernel_Name"].split("(")[0].replace("void ", "").split("<")[0]
+            v = float(r["Counter_Value"])
+            if "copyBuffer" in name:
+                if copy is None or v > copy:
+                    copy = v   # the calibration copy is the largest
+                continue
+            out.setdefault(name, []).append(v)
+        return {k: sum(v) / len(v) for k, v in out.items()}, copy
+
+    fetch, fcopy = per_kernel(fetch_csv, "FETCH_SIZE")
+    write, wcopy = per_kernel(write_csv, "WRITE_SIZE")
+    copy_bytes = int(os.environ.get("RFIM_COPY_BYTES", 768000000))
+    ff = copy_bytes / (fcopy * 1024.0)
+    wf = copy_bytes / (wcopy * 1024.0)
+    for k in sorted(set(fetch) & set(write)):
+        kern = k.split("::")[-1]
+        if kern.startswith("k_zero"):
+            continue
+        rb, wb = fetch[k] * 1024 * ff, write[k] * 1024 * wf
+        with open(os.path.join(PROFILES, f"traffic_{kern}_{workload}.txt"), "w") as f:
+            f.write(f"# HBM traffic of {kern} per launch, workload {workload}\n")
+            f.write(f"# commands: {command} with --pmc FETCH_SIZE, then with --pmc WRITE_SIZE\n")
+            f.write(f"# calibration: plain copy of {copy_bytes} bytes read {fcopy:.1f} KiB (FETCH_SIZE) "
+                    f"and wrote {wcopy:.1f} KiB (WRITE_SIZE): scale factors {ff:.4f} and {wf:.4f}\n")
+            f.write(f"kernel = {kern}\nsrc_hash = {source_hash()}\n")
+            f.write(f"fetch_kib_per_launch = {fetch[k]:.1f}\nwrite_kib_per_launch = {write[k]:.1f}\n")
+            f.write(f"read_bytes_per_launch = {rb:.0f}\nwrite_bytes_per_launch = {wb:.0f}\n")
+            f.write(f"traffic_bytes_per_launch = {rb + wb:.0f}\n")
+    print("profiles written", flush=True)
 
 
 def main():
@@ -36,7 +122,13 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain device copy of the batch size (for counter scaling)")
+    ap.add_argument("--summarize", nargs=3, metavar=("STATS_CSV", "FETCH_CSV", "WRITE_CSV"),
+                    help="write profiles/ summaries from rocprofv3 CSV output and exit")
+    ap.add_argument("--profile-command", default="")
     args = ap.parse_args()
+    if args.summarize:
+        summarize(*args.summarize, args.profile_command, f"arts40_{args.replace}")
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for {args.gpus}); beams are independent, "
               "so N GPUs would each run this workload on their own share.", file=sys.stderr)
@@ -101,9 +193,10 @@ def main():
     plan.set_timing(False)
     dom = max(kernels.items(), key=lambda kv: kv[1]["avg_ms"] * kv[1]["launches"])
     log("  kernels: " + json.dumps(kernels))
+    traffic = read_traffic(dom[0], f"arts40_{args.replace}")
     roof = {"bound": "hbm", "kernel": dom[0], "achieved": round(dom[1]["gbs"], 1),
             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(dom[1]["gbs"] / HBM_PEAK_GBS, 4),
-            "traffic": None}
+            "traffic": traffic, "algo_bytes": dom[1]["algo_bytes"]}
 
     if args.copy_calibration:
         a = torch.empty(in_bytes, dtype=torch.uint8, device=dev)

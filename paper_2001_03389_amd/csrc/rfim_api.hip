@@ -29,7 +29,7 @@ hipError_t launch_zero_u64(unsigned long long* p, int64_t n, hipStream_t s) {
 
 namespace {
 
-constexpr int kRing = 16;                 // descriptor staging slots per workspace
+constexpr int kRing = 64;                 // descriptor staging slots per workspace
 // fused-kernel tile LDS per work-group: 160 KB per CU shared by 3 work-groups,
 // less the kernel's static LDS (TD exception worklist and counters)
 constexpr size_t kLdsBudget = 51200;
@@ -199,6 +199,8 @@ struct Workspace {
     bool has_last = false;
     Slot ring[kRing];
     int next = 0;
+    hipStream_t aux = nullptr;          // second stream of the chunked schedule
+    std::vector<hipEvent_t> chunk_ev;   // events of the chunked schedule
 
     ~Workspace() {
         if (has_last) (void)hipEventSynchronize(last_done);
@@ -212,6 +214,20 @@ struct Workspace {
         }
         if (d_work) (void)hipFree(d_work);
         if (last_done) (void)hipEventDestroy(last_done);
+        for (hipEvent_t e : chunk_ev) (void)hipEventDestroy(e);
+        if (aux) (void)hipStreamDestroy(aux);
+    }
+
+    // the auxiliary stream and at least n events for the chunked schedule
+    rfim_status chunk_resources(size_t n) {
+        if (!aux && hipStreamCreateWithFlags(&aux, hipStreamNonBlocking) != hipSuccess)
+            return RFIM_ERR_DEVICE;
+        while (chunk_ev.size() < n) {
+            hipEvent_t e = nullptr;
+            if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return RFIM_ERR_DEVICE;
+            chunk_ev.push_back(e);
+        }
+        return RFIM_OK;
     }
 
     rfim_status init(int dev) {
@@ -318,6 +334,12 @@ rfim_status device_workspace(Workspace** out) {
 
 // Everything one call needs to know about its launches.
 struct LaunchPlan {
+    // uint8 beams are processed in chunks of consecutive beams (by index in
+    // u8_beams): chunk i is [chunk_begin[i], chunk_begin[i+1]).  With a TD
+    // run, the row-statistics kernel of chunk i+1 (on an internal stream) runs
+    // beside the fused kernel of chunk i, whose reads then come mostly from the
+    // 256 MB Infinity Cache because chunk i was just read.
+    std::vector<int> chunk_begin;
     std::vector<Segment> segs;
     std::vector<int> u8_beams;   // indices of uint8 beams
     std::vector<int> f32_beams;  // indices of float32 beams
@@ -370,6 +392,29 @@ rfim_status make_launch_plan(const rfim_beam* beams, int32_t nbeams, const rfim_
     if (!lp->f32_beams.empty()) return RFIM_ERR_UNSUPPORTED;
     if (lp->u8_rows >= ((int64_t)1 << 31) || lp->u8_tiles >= ((int64_t)1 << 31))
         return RFIM_ERR_UNSUPPORTED;
+    {
+        static const size_t chunk_bytes = [] {
+            // off by default: measured slower on the 40-beam workload (3.1 vs
+            // 1.5 ms per step) because the small per-chunk launches lose more
+            // than the cache reuse gains
+            const char* e = std::getenv("RFIM_CHUNK_MB");
+            long v = e ? std::atol(e) : 0;
+            return (size_t)(v > 0 ? v : 0) << 20;
+        }();
+        size_t acc = 0;
+        lp->chunk_begin.clear();
+        lp->chunk_begin.push_back(0);
+        for (int j = 0; j < (int)lp->u8_beams.size(); j++) {
+            const rfim_beam& b = beams[lp->u8_beams[j]];
+            const size_t bytes = (size_t)b.nchan * (size_t)b.nsamp;
+            if (chunk_bytes && acc > 0 && acc + bytes > chunk_bytes) {
+                lp->chunk_begin.push_back(j);
+                acc = 0;
+            }
+            acc += bytes;
+        }
+        lp->chunk_begin.push_back((int)lp->u8_beams.size());
+    }
     lp->rec_bytes = (size_t)lp->u8_rows * std::max(1, lp->max_td) * 4;
     lp->rec_bytes = (lp->rec_bytes + 255) & ~(size_t)255;
     lp->count_bytes = want_counts ? (size_t)nbeams * 8 * sizeof(unsigned long long) : 0;
@@ -400,53 +445,86 @@ rfim_status execute(const rfim_beam* beams, int32_t nbeams, const LaunchPlan& lp
         if (st != RFIM_OK) return st;
     }
     const int nu8 = (int)lp.u8_beams.size();
+    const int nchunks = (int)lp.chunk_begin.size() - 1;
     for (size_t si = 0; si < lp.segs.size() && nu8 > 0; si++) {
         Segment seg = lp.segs[si];
         bool any_flags = false;
-        std::vector<DevBeam> tab(nu8);
-        int64_t row = 0, tile = 0;
-        for (int j = 0; j < nu8; j++) {
-            const rfim_beam& b = beams[lp.u8_beams[j]];
-            DevBeam& d = tab[j];
-            d.in = si == 0 ? b.in : b.out;
-            d.out = b.out;
-            d.flags = b.flags;
-            d.C = b.nchan;
-            d.T = b.nsamp;
-            d.stride = b.row_stride;
-            d.row0 = row;
-            d.tile0 = tile;
-            d.Tt = lp.Tt[lp.u8_beams[j]];
-            d.Cp = lp.Cp[lp.u8_beams[j]];
-            d.cidx = lp.u8_beams[j];
-            d.pad = 0;
-            row += b.nchan;
-            tile += (b.nsamp + d.Tt - 1) / d.Tt;
-            any_flags |= b.flags != nullptr;
-        }
+        for (int j = 0; j < nu8; j++) any_flags |= beams[lp.u8_beams[j]].flags != nullptr;
         seg.flags_mode = any_flags ? (si == 0 ? 1 : 2) : 0;
-        Slot* sl = nullptr;
-        size_t bytes = sizeof(DevBeam) * (size_t)nu8;
-        st = ws.slot(bytes, &sl);
-        if (st != RFIM_OK) return st;
-        std::memcpy(sl->h, tab.data(), bytes);
-        st = dev_err(hipMemcpyAsync(sl->d, sl->h, bytes, hipMemcpyHostToDevice, stream));
-        if (st != RFIM_OK) return st;
-        const DevBeam* d_tab = (const DevBeam*)sl->d;
-        if (seg.n_td > 0) {
-            st = dev_err(ws.timed_launch(RFIM_KERNEL_TD_ROWS_U8, stream, [&] {
-                return launch_td_rows_u8(d_tab, nu8, lp.u8_rows, seg, d_rec, d_counts, 8, stream);
+        const bool chunked = seg.n_td > 0 && nchunks > 1;
+        hipStream_t ts = stream;   // stream of the row-statistics kernels
+        if (chunked) {
+            st = ws.chunk_resources(1 + 2 * (size_t)nchunks);
+            if (st != RFIM_OK) return st;
+            ts = ws.aux;
+            // fork: the aux stream starts after everything already on `stream`
+            if (hipEventRecord(ws.chunk_ev[0], stream) != hipSuccess ||
+                hipStreamWaitEvent(ts, ws.chunk_ev[0], 0) != hipSuccess)
+                return RFIM_ERR_DEVICE;
+        }
+        const int nparts = chunked ? nchunks : 1;
+        int64_t row_base = 0;
+        for (int ci = 0; ci < nparts; ci++) {
+            const int jb = chunked ? lp.chunk_begin[ci] : 0, je = chunked ? lp.chunk_begin[ci + 1] : nu8;
+            const int nt = je - jb;
+            std::vector<DevBeam> tab(nt);
+            int64_t row = 0, tile = 0;
+            for (int j = 0; j < nt; j++) {
+                const int bi = lp.u8_beams[jb + j];
+                const rfim_beam& b = beams[bi];
+                DevBeam& d = tab[j];
+                d.in = si == 0 ? b.in : b.out;
+                d.out = b.out;
+                d.flags = b.flags;
+                d.C = b.nchan;
+                d.T = b.nsamp;
+                d.stride = b.row_stride;
+                d.row0 = row;
+                d.tile0 = tile;
+                d.Tt = lp.Tt[bi];
+                d.Cp = lp.Cp[bi];
+                d.cidx = bi;
+                d.pad = 0;
+                row += b.nchan;
+                tile += (b.nsamp + d.Tt - 1) / d.Tt;
+            }
+            Slot* sl = nullptr;
+            const size_t bytes = sizeof(DevBeam) * (size_t)nt;
+            st = ws.slot(bytes, &sl);
+            if (st != RFIM_OK) return st;
+            std::memcpy(sl->h, tab.data(), bytes);
+            if (chunked && ci >= 2) {
+                // keep the statistics at most two chunks ahead of the fused
+                // pass, so the chunk it reads is still cached
+                if (hipStreamWaitEvent(ts, ws.chunk_ev[1 + 2 * (ci - 2) + 1], 0) != hipSuccess)
+                    return RFIM_ERR_DEVICE;
+            }
+            st = dev_err(hipMemcpyAsync(sl->d, sl->h, bytes, hipMemcpyHostToDevice, ts));
+            if (st != RFIM_OK) return st;
+            const DevBeam* d_tab = (const DevBeam*)sl->d;
+            uint32_t* rec = d_rec + row_base * std::max(1, seg.n_td);
+            if (seg.n_td > 0) {
+                st = dev_err(ws.timed_launch(RFIM_KERNEL_TD_ROWS_U8, ts, [&] {
+                    return launch_td_rows_u8(d_tab, nt, row, seg, rec, d_counts, 8, ts);
+                }));
+                if (st != RFIM_OK) return st;
+            }
+            if (chunked) {
+                hipEvent_t td_done = ws.chunk_ev[1 + 2 * ci];
+                if (hipEventRecord(td_done, ts) != hipSuccess || hipStreamWaitEvent(stream, td_done, 0) != hipSuccess)
+                    return RFIM_ERR_DEVICE;
+            }
+            const bool vec = fd_vec_ok(beams, lp, seg);
+            st = dev_err(ws.timed_launch(RFIM_KERNEL_FUSED_U8, stream, [&] {
+                return launch_fused_u8(d_tab, nt, tile, seg, rec, lp.u8_lds, vec, d_counts, 8, stream);
             }));
             if (st != RFIM_OK) return st;
+            if (chunked && hipEventRecord(ws.chunk_ev[1 + 2 * ci + 1], stream) != hipSuccess)
+                return RFIM_ERR_DEVICE;
+            if (hipEventRecord(sl->ev, stream) != hipSuccess) return RFIM_ERR_DEVICE;
+            sl->used = true;
+            row_base += row;
         }
-        const bool vec = fd_vec_ok(beams, lp, seg);
-        st = dev_err(ws.timed_launch(RFIM_KERNEL_FUSED_U8, stream, [&] {
-            return launch_fused_u8(d_tab, nu8, lp.u8_tiles, seg, d_rec, lp.u8_lds, vec, d_counts, 8,
-                                   stream);
-        }));
-        if (st != RFIM_OK) return st;
-        if (hipEventRecord(sl->ev, stream) != hipSuccess) return RFIM_ERR_DEVICE;
-        sl->used = true;
     }
     if (hipEventRecord(ws.last_done, stream) != hipSuccess) return RFIM_ERR_DEVICE;
     ws.last_stream = stream;

@@ -114,7 +114,7 @@ __device__ inline void store4(uint8_t* p, uint32_t v, int64_t t, int64_t T) {
 namespace {
 
 constexpr int kHistCopies = 4;     // per wave, lane & 3 picks the copy
-constexpr int kHistPitch = 260;    // words per copy (offsets the banks of copies)
+constexpr int kHistPitch = 272;    // words per copy (copies 16 banks apart)
 constexpr int kRowsPerWG = kBlock / 64;
 
 // Sum over the 64 lanes with DPP row rotations (every lane of a 16-lane row
@@ -187,9 +187,10 @@ __device__ inline uint32_t td_keep_interval(uint64_t n, uint64_t S1, u128 D, con
                                             int* lo, int* hi) {
     uint32_t bits = 0;
     int l = 256, h = -1;
+    const double kd2 = kx.k * kx.k, Dd = (double)D;
 #pragma unroll 1
     for (int u = 0; u < 4; u++) {
-        const bool kp = td_keeps_u8(n, S1, D, 4 * lane + u, kx);
+        const bool kp = td_keeps_u8(n, S1, D, kd2, Dd, 4 * lane + u, kx);
         bits |= (kp ? 1u : 0u) << u;
         const uint64_t km = __ballot(kp);
         if (km) {
