@@ -69,7 +69,9 @@ typedef enum { RFIM_TD = 0, RFIM_FD = 1 } rfim_domain;
  * overwritten), otherwise the two must not overlap.  `flags` (device, may be
  * NULL) is a [nchan][row_stride] uint8 array whose bit j is set where step j
  * replaced the sample; requires nsteps <= 8.  Constraints: 1 <= nchan < 2^31,
- * 1 <= nsamp < 2^31, row_stride >= nsamp. */
+ * 1 <= nsamp < 2^31, row_stride >= nsamp.  float32 beams: values must be
+ * finite; nchan and nsamp below 2^24, and nchan <= 19660 when the steps
+ * include FD, else RFIM_ERR_UNSUPPORTED. */
 typedef struct {
     int32_t dtype;    /* rfim_dtype */
     int32_t reserved; /* must be 0 */
@@ -118,6 +120,36 @@ rfim_status rfim_plan_create(const rfim_beam* shapes, int32_t nbeams, const rfim
                              int32_t nsteps, const char* tune_cache_path, rfim_plan** out);
 rfim_status rfim_plan_destroy(rfim_plan* plan);
 
+/* HIP-graph form of a plan (batched runs replayed without host work):
+ * rfim_plan_capture records one run of the plan on these beams (shapes as the
+ * plan's; the buffers are baked into the graph) into a graph owned by the
+ * plan, replacing any earlier one; rfim_plan_replay launches it on `stream`.
+ * The graph holds only kernel nodes (its beam tables are written once, at
+ * capture).  Replays of one plan must not overlap. */
+rfim_status rfim_plan_capture(rfim_plan* plan, const rfim_beam* beams, int32_t nbeams, void* stream);
+rfim_status rfim_plan_replay(rfim_plan* plan, void* stream);
+
+/* Auto-tuner (Section III: parameters tuned per setup and platform, the
+ * configurations saved for production).  Times every candidate kernel
+ * configuration for these shapes and steps on freshly allocated beams filled
+ * with a deterministic pattern, rejects candidates whose outputs or flags
+ * differ from the default configuration's by a single byte, and stores the
+ * fastest in the JSON cache file tune_cache_path (created or updated), where
+ * rfim_plan_create finds it.  Synchronises `stream`; allocates (hipMalloc)
+ * twice the shapes' bytes for the duration of the call.  *best_ms (may be
+ * NULL) receives the best time per run. */
+rfim_status rfim_autotune(const rfim_beam* shapes, int32_t nbeams, const rfim_step* steps, int32_t nsteps,
+                          const char* tune_cache_path, void* stream, double* best_ms);
+
+/* Tuning-cache access without a GPU: rfim_tune_lookup fills out3 =
+ * {uint8 tile cap, float32 LDS bytes, float32 tile cap} for the key of these
+ * shapes and steps (RFIM_ERR_UNSUPPORTED: no entry or no file);
+ * rfim_tune_store adds or replaces that entry. */
+rfim_status rfim_tune_lookup(const char* path, const rfim_beam* shapes, int32_t nbeams, const rfim_step* steps,
+                             int32_t nsteps, int64_t* out3);
+rfim_status rfim_tune_store(const char* path, const rfim_beam* shapes, int32_t nbeams, const rfim_step* steps,
+                            int32_t nsteps, const int64_t* params3, double ms);
+
 /* Per (beam, step) number of replaced samples of the most recent run with
  * this plan, copied to host_out[nbeams * nsteps]; synchronises the plan's
  * last stream. */
@@ -125,9 +157,13 @@ rfim_status rfim_plan_flag_counts(const rfim_plan* plan, uint64_t* host_out);
 
 /* Kernels the library launches, for per-kernel timing. */
 typedef enum {
-    RFIM_KERNEL_TD_ROWS_U8 = 0, /* uint8 row statistics + TD decisions */
-    RFIM_KERNEL_FUSED_U8 = 1,   /* uint8 TD apply + FD steps + write-back */
-    RFIM_KERNEL_KINDS = 2
+    RFIM_KERNEL_TD_ROWS_U8 = 0,  /* uint8 row statistics + TD decisions */
+    RFIM_KERNEL_FUSED_U8 = 1,    /* uint8 TD apply + FD steps + write-back */
+    RFIM_KERNEL_TD_ROWS_F32 = 2, /* float32 register-resident rows: TD steps */
+    RFIM_KERNEL_FUSED_F32 = 3,   /* float32 TD apply + FD steps + write-back */
+    RFIM_KERNEL_TD_WIDE_F32 = 4, /* float32 rows outside the fast window */
+    RFIM_KERNEL_FD_WIDE_F32 = 5, /* float32 time samples outside the fast window */
+    RFIM_KERNEL_KINDS = 6
 } rfim_kernel_kind;
 
 /* Per-kernel timing of a plan (Section V-B reports execution time averaged

@@ -22,7 +22,10 @@ RFIM_U8, RFIM_F32 = 0, 1
 RFIM_REPLACE_MEAN, RFIM_REPLACE_MEDIAN = 0, 1
 RFIM_TD, RFIM_FD = 0, 1
 RFIM_KERNEL_TD_ROWS_U8, RFIM_KERNEL_FUSED_U8 = 0, 1
-KERNEL_NAMES = {RFIM_KERNEL_TD_ROWS_U8: "k_td_rows_u8", RFIM_KERNEL_FUSED_U8: "k_fused_u8"}
+RFIM_KERNEL_TD_ROWS_F32, RFIM_KERNEL_FUSED_F32, RFIM_KERNEL_TD_WIDE_F32, RFIM_KERNEL_FD_WIDE_F32 = 2, 3, 4, 5
+KERNEL_NAMES = {RFIM_KERNEL_TD_ROWS_U8: "k_td_rows_u8", RFIM_KERNEL_FUSED_U8: "k_fused_u8",
+                RFIM_KERNEL_TD_ROWS_F32: "k_td_rows_f32", RFIM_KERNEL_FUSED_F32: "k_fused_f32",
+                RFIM_KERNEL_TD_WIDE_F32: "k_td_wide_f32", RFIM_KERNEL_FD_WIDE_F32: "k_fd_wide_f32"}
 
 
 class RfimError(RuntimeError):
@@ -65,9 +68,15 @@ def lib() -> ctypes.CDLL:
         L.rfim_plan_set_timing.argtypes = [vp, i32]
         L.rfim_plan_kernel_times.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_uint64),
                                              ctypes.POINTER(ctypes.c_double)]
+        L.rfim_plan_capture.argtypes = [vp, PB, i32, vp]
+        L.rfim_plan_replay.argtypes = [vp, vp]
+        L.rfim_autotune.argtypes = [PB, i32, PS, i32, ctypes.c_char_p, vp, ctypes.POINTER(dbl)]
+        L.rfim_tune_lookup.argtypes = [ctypes.c_char_p, PB, i32, PS, i32, ctypes.POINTER(i64)]
+        L.rfim_tune_store.argtypes = [ctypes.c_char_p, PB, i32, PS, i32, ctypes.POINTER(i64), dbl]
         for f in ("rfim_td_sigma_cut", "rfim_fd_sigma_cut", "rfim_pipeline_run", "rfim_plan_create",
                   "rfim_plan_destroy", "rfim_plan_flag_counts", "rfim_plan_set_timing",
-                  "rfim_plan_kernel_times"):
+                  "rfim_plan_kernel_times", "rfim_plan_capture", "rfim_plan_replay", "rfim_autotune",
+                  "rfim_tune_lookup", "rfim_tune_store"):
             getattr(L, f).restype = st
         L.rfim_status_string.argtypes = [st]
         L.rfim_status_string.restype = ctypes.c_char_p
@@ -154,6 +163,57 @@ def _beams(inputs, outputs, flags, nsamp):
     return arr, n
 
 
+def shape_beam(dtype: str, nchan: int, nsamp: int, row_stride: int | None = None,
+               flags: bool = False) -> rfim_beam:
+    """A beam descriptor that carries only a shape (plans, the tuner and the
+    tuning cache ignore pointers); the pointers are dummies."""
+    b = rfim_beam()
+    b.dtype = {"u8": RFIM_U8, "f32": RFIM_F32}.get(dtype, dtype)
+    b.reserved = 0
+    b.nchan, b.nsamp = int(nchan), int(nsamp)
+    b.row_stride = int(row_stride if row_stride is not None else nsamp)
+    b.in_ = b.out = 4096
+    b.flags = 8192 if flags else None
+    return b
+
+
+def _shape_array(shapes):
+    arr = (rfim_beam * max(1, len(shapes)))()
+    for i, b in enumerate(shapes):
+        arr[i] = b
+    return arr
+
+
+def tune_lookup(path: str, shapes: Sequence[rfim_beam], steps: Sequence):
+    """(uint8 tile cap, float32 LDS bytes, float32 tile cap) stored in the
+    tuning cache for these shapes and steps, or None (rfim_tune_lookup)."""
+    out = (ctypes.c_int64 * 3)()
+    rc = lib().rfim_tune_lookup(path.encode(), _shape_array(shapes), len(shapes), make_steps(steps),
+                                len(steps), out)
+    if rc == RFIM_ERR_UNSUPPORTED:
+        return None
+    _check(rc, "rfim_tune_lookup")
+    return int(out[0]), int(out[1]), int(out[2])
+
+
+def tune_store(path: str, shapes: Sequence[rfim_beam], steps: Sequence, params, ms: float = 0.0) -> None:
+    """Adds or replaces the cache entry of these shapes and steps (rfim_tune_store)."""
+    p = (ctypes.c_int64 * 3)(*[int(v) for v in params])
+    _check(lib().rfim_tune_store(path.encode(), _shape_array(shapes), len(shapes), make_steps(steps),
+                                 len(steps), p, float(ms)), "rfim_tune_store")
+
+
+def autotune(shapes: Sequence[rfim_beam], steps: Sequence, cache_path: str, stream=None) -> float:
+    """Times the candidate kernel configurations for these shapes and steps,
+    stores the fastest bit-identical one in the cache; returns its time per
+    run in ms (rfim_autotune)."""
+    best = ctypes.c_double()
+    _check(lib().rfim_autotune(_shape_array(shapes), len(shapes), make_steps(steps), len(steps),
+                               cache_path.encode(), _stream_handle(stream), ctypes.byref(best)),
+           "rfim_autotune")
+    return float(best.value)
+
+
 def _stream_handle(stream):
     if stream is None:
         import torch
@@ -206,6 +266,15 @@ class Plan:
                                     tune_cache.encode() if tune_cache else None, ctypes.byref(h))
         _check(rc, "rfim_plan_create")
         self.handle = h
+
+    def capture(self, inputs: Sequence, outputs=None, flags=None, nsamp=None, stream=None) -> None:
+        """Records one run on these buffers into the plan's HIP graph (rfim_plan_capture)."""
+        arr, n = _beams(inputs, outputs, flags, nsamp)
+        _check(lib().rfim_plan_capture(self.handle, arr, n, _stream_handle(stream)), "rfim_plan_capture")
+
+    def replay(self, stream=None) -> None:
+        """Launches the captured graph (rfim_plan_replay)."""
+        _check(lib().rfim_plan_replay(self.handle, _stream_handle(stream)), "rfim_plan_replay")
 
     def flag_counts(self):
         buf = (ctypes.c_uint64 * (self.nbeams * self.nsteps))()

@@ -1,6 +1,7 @@
 // Host side of the C ABI declared in include/rfim.h: argument validation,
-// splitting a step list into runs of [TD steps][FD steps], per-launch beam
-// tables, workspaces, plans and kernel launches.
+// splitting a step list into runs of [TD steps][FD steps], launch planning
+// (kernel shapes per beam), the launch program of a call (beam tables + an
+// ordered list of kernel launches), workspaces, plans and HIP-graph capture.
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
@@ -11,6 +12,7 @@
 #include <vector>
 
 #include "rfim_internal.h"
+#include "rfim_tune.h"
 
 namespace rfim {
 
@@ -27,44 +29,46 @@ hipError_t launch_zero_u64(unsigned long long* p, int64_t n, hipStream_t s) {
     return hipGetLastError();
 }
 
-namespace {
-
-constexpr int kRing = 64;                 // descriptor staging slots per workspace
-// fused-kernel tile LDS per work-group: 160 KB per CU shared by 3 work-groups,
-// less the kernel's static LDS (TD exception worklist and counters)
-constexpr size_t kLdsBudget = 51200;
-constexpr size_t kLdsMax = 65536;
-
 KExact make_k(double k) {
+    // the exact binary value k = mk * 2^ek (mk odd) is kept for every k > 0:
+    // the float32 wide path compares against sums far beyond 2^128
     KExact r{};
     r.k = k;
+    if (k > 0.0) {
+        int e = 0;
+        double f = std::frexp(k, &e);
+        uint64_t mk = (uint64_t)std::ldexp(f, 53);
+        int ek = e - 53;
+        while ((mk & 1) == 0) {
+            mk >>= 1;
+            ek++;
+        }
+        unsigned __int128 m2 = (unsigned __int128)mk * mk;
+        r.mk2_lo = (uint64_t)m2;
+        r.mk2_hi = (uint64_t)(m2 >> 64);
+        r.mk2_bits = 0;
+        for (unsigned __int128 t = m2; t; t >>= 1) r.mk2_bits++;
+        r.ek = ek;
+    }
     if (k < std::ldexp(1.0, -64)) {   // includes 0: k^2 * V < 1 for every V < 2^128
         r.mode = 1;
-        return r;
-    }
-    if (k >= std::ldexp(1.0, 20)) {   // k^2 >= 2^40 > n - 1: nothing can be cut
+    } else if (k >= std::ldexp(1.0, 20)) {   // k^2 >= 2^40 > n - 1 and > C: nothing can be cut
         r.mode = 2;
-        return r;
+    } else {
+        r.mode = 0;
     }
-    int e = 0;
-    double f = std::frexp(k, &e);
-    uint64_t mk = (uint64_t)std::ldexp(f, 53);
-    int ek = e - 53;
-    while ((mk & 1) == 0) {
-        mk >>= 1;
-        ek++;
-    }
-    unsigned __int128 m2 = (unsigned __int128)mk * mk;
-    r.mk2_lo = (uint64_t)m2;
-    r.mk2_hi = (uint64_t)(m2 >> 64);
-    r.mk2_bits = 0;
-    for (unsigned __int128 t = m2; t; t >>= 1) r.mk2_bits++;
-    r.ek = ek;
-    r.mode = 0;
     return r;
 }
 
 size_t elem_size(int32_t dt) { return dt == RFIM_U8 ? 1 : 4; }
+
+namespace {
+
+constexpr int kRing = 64;   // table staging slots per workspace
+// uint8 fused-kernel tile LDS per work-group: 160 KB per CU shared by three
+// work-groups, less the kernel's static LDS (TD exception worklist, counters)
+constexpr size_t kLdsBudget = 51200;
+constexpr size_t kLdsMax = 65536;
 
 bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
     uintptr_t x = (uintptr_t)a, y = (uintptr_t)b;
@@ -74,6 +78,74 @@ bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
 size_t beam_span(const rfim_beam& b) {
     return (size_t)((b.nchan - 1) * b.row_stride + b.nsamp) * elem_size(b.dtype);
 }
+
+// The step list as runs of [consecutive TD steps][consecutive FD steps].
+std::vector<Segment> segments_of(const rfim_step* steps, int32_t nsteps) {
+    std::vector<Segment> out;
+    int s = 0;
+    while (s < nsteps) {
+        Segment seg;
+        std::memset(&seg, 0, sizeof(seg));
+        while (s < nsteps && steps[s].domain == RFIM_TD) {
+            SegStep& d = seg.td[seg.n_td++];
+            d.kx = make_k(steps[s].k);
+            d.replace = steps[s].replace;
+            d.bit = s < 8 ? s : -1;
+            d.bin = 0;
+            s++;
+        }
+        while (s < nsteps && steps[s].domain == RFIM_FD) {
+            SegStep& d = seg.fd[seg.n_fd++];
+            d.kx = make_k(steps[s].k);
+            d.replace = steps[s].replace;
+            d.bit = s < 8 ? s : -1;
+            d.bin = steps[s].bin_size;
+            s++;
+        }
+        out.push_back(seg);
+    }
+    return out;
+}
+
+// uint8 fused-kernel tile for one beam: Tt samples (power of two in [4, cap])
+// and Cp LDS bytes per time sample
+bool tile_shape_u8(const rfim_beam& b, bool flags, int cap, int32_t* Tt, int32_t* Cp) {
+    if (b.nchan >= ((int64_t)1 << 24)) return false;   // worklist packs the row in 24 bits
+    // 16-byte aligned time samples (vector LDS reads), padded off a multiple
+    // of 256 bytes so the transposed stores of neighbouring lanes spread over banks
+    int64_t cp = ((b.nchan + 15) / 16) * 16;
+    if (cp % 256 == 0 || cp % 256 == 128) cp += 16;
+    size_t per = (size_t)cp * (flags ? 2 : 1);
+    int t = 4;
+    while (t * 2 <= cap && t < 64) t *= 2;
+    while (t > 4 && per * t > kLdsBudget) t >>= 1;
+    if (per * t > kLdsMax) return false;
+    *Tt = t;
+    *Cp = (int32_t)cp;
+    return true;
+}
+
+// LDS a work-group may use (the device limit, queried once)
+size_t lds_limit() {
+    static size_t lim = [] {
+        int dev = 0, v = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || v <= 0)
+            return (size_t)65536;
+        return (size_t)v;
+    }();
+    return lim;
+}
+
+struct Slot {
+    void* h = nullptr;  // pinned staging
+    void* d = nullptr;  // device copy read by the kernels
+    size_t cap = 0;
+    hipEvent_t ev = nullptr;
+    bool used = false;
+};
+
+}  // namespace
 
 rfim_status validate(const rfim_beam* beams, int32_t nbeams, const rfim_step* steps,
                      int32_t nsteps) {
@@ -113,73 +185,6 @@ rfim_status validate(const rfim_beam* beams, int32_t nbeams, const rfim_step* st
     return RFIM_OK;
 }
 
-// The step list as runs of [consecutive TD steps][consecutive FD steps].
-std::vector<Segment> segments_of(const rfim_step* steps, int32_t nsteps) {
-    std::vector<Segment> out;
-    int s = 0;
-    while (s < nsteps) {
-        Segment seg;
-        std::memset(&seg, 0, sizeof(seg));
-        while (s < nsteps && steps[s].domain == RFIM_TD) {
-            SegStep& d = seg.td[seg.n_td++];
-            d.kx = make_k(steps[s].k);
-            d.replace = steps[s].replace;
-            d.bit = s < 8 ? s : -1;
-            d.bin = 0;
-            s++;
-        }
-        while (s < nsteps && steps[s].domain == RFIM_FD) {
-            SegStep& d = seg.fd[seg.n_fd++];
-            d.kx = make_k(steps[s].k);
-            d.replace = steps[s].replace;
-            d.bit = s < 8 ? s : -1;
-            d.bin = steps[s].bin_size;
-            s++;
-        }
-        out.push_back(seg);
-    }
-    return out;
-}
-
-// Tile geometry of the fused kernel for one beam.
-// Largest fused-kernel tile width allowed (samples, power of two in [4, 64]);
-// RFIM_TILE_T in the environment caps it (tuning experiments).
-int tile_cap() {
-    static int cap = [] {
-        const char* e = std::getenv("RFIM_TILE_T");
-        int v = e ? std::atoi(e) : 64;
-        int p = 4;
-        while (p * 2 <= v && p < 64) p *= 2;
-        return p;
-    }();
-    return cap;
-}
-
-bool tile_shape(const rfim_beam& b, bool flags, int32_t* Tt, int32_t* Cp) {
-    if (b.nchan >= ((int64_t)1 << 24)) return false;   // worklist packs the row in 24 bits
-    // 16-byte aligned time samples (vector LDS reads), padded off a multiple
-    // of 256 bytes so the transposed stores of neighbouring lanes spread over banks
-    int64_t cp = ((b.nchan + 15) / 16) * 16;
-    if (cp % 256 == 0 || cp % 256 == 128) cp += 16;
-    size_t per = (size_t)cp * (flags ? 2 : 1);
-    int t = tile_cap();
-    while (t > 4 && per * t > kLdsBudget) t >>= 1;
-    if (per * t > kLdsMax) return false;
-    *Tt = t;
-    *Cp = (int32_t)cp;
-    return true;
-}
-
-struct Slot {
-    void* h = nullptr;  // pinned staging
-    void* d = nullptr;  // device copy read by the kernels
-    size_t cap = 0;
-    hipEvent_t ev = nullptr;
-    bool used = false;
-};
-
-}  // namespace
-
 struct TimedLaunch {
     int kind;
     hipEvent_t a, b;
@@ -199,8 +204,6 @@ struct Workspace {
     bool has_last = false;
     Slot ring[kRing];
     int next = 0;
-    hipStream_t aux = nullptr;          // second stream of the chunked schedule
-    std::vector<hipEvent_t> chunk_ev;   // events of the chunked schedule
 
     ~Workspace() {
         if (has_last) (void)hipEventSynchronize(last_done);
@@ -214,20 +217,6 @@ struct Workspace {
         }
         if (d_work) (void)hipFree(d_work);
         if (last_done) (void)hipEventDestroy(last_done);
-        for (hipEvent_t e : chunk_ev) (void)hipEventDestroy(e);
-        if (aux) (void)hipStreamDestroy(aux);
-    }
-
-    // the auxiliary stream and at least n events for the chunked schedule
-    rfim_status chunk_resources(size_t n) {
-        if (!aux && hipStreamCreateWithFlags(&aux, hipStreamNonBlocking) != hipSuccess)
-            return RFIM_ERR_DEVICE;
-        while (chunk_ev.size() < n) {
-            hipEvent_t e = nullptr;
-            if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return RFIM_ERR_DEVICE;
-            chunk_ev.push_back(e);
-        }
-        return RFIM_OK;
     }
 
     rfim_status init(int dev) {
@@ -262,7 +251,7 @@ struct Workspace {
     // brackets one launch with events when timing is on
     template <typename F>
     hipError_t timed_launch(int kind, hipStream_t s, F&& launch) {
-        if (!timing) return launch();
+        if (!timing || kind < 0) return launch();
         hipEvent_t a = take_event(), b = take_event();
         if (!a || !b) return hipErrorOutOfMemory;
         hipError_t e = hipEventRecord(a, s);
@@ -332,23 +321,30 @@ rfim_status device_workspace(Workspace** out) {
     return RFIM_OK;
 }
 
-// Everything one call needs to know about its launches.
+// Kernel shapes of a call, chosen from the beam shapes, the steps and the
+// tuning parameters.
 struct LaunchPlan {
-    // uint8 beams are processed in chunks of consecutive beams (by index in
-    // u8_beams): chunk i is [chunk_begin[i], chunk_begin[i+1]).  With a TD
-    // run, the row-statistics kernel of chunk i+1 (on an internal stream) runs
-    // beside the fused kernel of chunk i, whose reads then come mostly from the
-    // 256 MB Infinity Cache because chunk i was just read.
-    std::vector<int> chunk_begin;
+    TuneParams tune;
     std::vector<Segment> segs;
     std::vector<int> u8_beams;   // indices of uint8 beams
     std::vector<int> f32_beams;  // indices of float32 beams
-    std::vector<int32_t> Tt, Cp; // per beam
+    std::vector<int32_t> Tt, Cp; // uint8 tile per beam
     int64_t u8_rows = 0, u8_tiles = 0;
     size_t u8_lds = 0;
     int max_td = 0;
-    size_t rec_bytes = 0, count_bytes = 0;
     int nsteps = 0;
+    // float32: TD kernel shape per beam (nt x vpt; nt == 0: every row wide),
+    // fused-kernel shape per segment and beam (fast FD bin B, 0 = none)
+    std::vector<int32_t> f_nt, f_vpt;
+    struct F32Shape {
+        int32_t B = 0, bpl = 1, Tt = 64, Cp = 0;
+        size_t lds = 0;
+    };
+    std::vector<std::vector<F32Shape>> f_shape;   // [segment][float32 beam]
+    int64_t f32_rows = 0, f32_cols = 0, f32_maxC = 0;
+    // workspace layout (byte offsets)
+    size_t off_u8rec = 0, off_f32rec = 0, off_wide = 0, off_tditems = 0, off_fditems = 0;
+    size_t count_bytes = 0, work_bytes = 0;
 };
 
 // True when, for every uint8 beam and FD step of the run, each lane's share
@@ -369,8 +365,69 @@ bool fd_vec_ok(const rfim_beam* beams, const LaunchPlan& lp, const Segment& seg)
     return true;
 }
 
+// Shapes of the float32 kernels for every float32 beam of the call.
+rfim_status plan_f32(const rfim_beam* beams, LaunchPlan* lp) {
+    const int nf = (int)lp->f32_beams.size();
+    lp->f_nt.assign(nf, 0);
+    lp->f_vpt.assign(nf, 0);
+    lp->f_shape.assign(lp->segs.size(), std::vector<LaunchPlan::F32Shape>(nf));
+    bool any_fd = false;
+    for (auto& sg : lp->segs) any_fd |= sg.n_fd > 0;
+    const size_t budget = std::min(lp->tune.f32_lds, lds_limit());
+    for (int j = 0; j < nf; j++) {
+        const rfim_beam& b = beams[lp->f32_beams[j]];
+        // exact wide sums are sized for fewer than 2^24 samples per row / column
+        if (b.nchan >= ((int64_t)1 << 24) || b.nsamp >= ((int64_t)1 << 24)) return RFIM_ERR_UNSUPPORTED;
+        // a time sample of the wide FD kernel lives in LDS (value + flag byte)
+        if (any_fd && (size_t)b.nchan * 5 > 98304) return RFIM_ERR_UNSUPPORTED;
+        const int64_t T = b.nsamp;
+        int nt = 0, vpt = 0;
+        if (T <= 256) { nt = 256; vpt = 1; }
+        else if (T <= 1024) { nt = 256; vpt = 4; }
+        else if (T <= 4096) { nt = 256; vpt = 16; }
+        else if (T <= 8192) { nt = 1024; vpt = 8; }
+        else if (T <= 16384) { nt = 1024; vpt = 16; }
+        else if (T <= 32768) { nt = 1024; vpt = 32; }
+        else if (T <= 65536) { nt = 1024; vpt = 64; }
+        lp->f_nt[j] = nt;   // 0: rows longer than the register-resident kernel holds go wide
+        lp->f_vpt[j] = vpt;
+        lp->f32_rows += b.nchan;
+        lp->f32_cols += b.nsamp;
+        lp->f32_maxC = std::max<int64_t>(lp->f32_maxC, b.nchan);
+        for (size_t si = 0; si < lp->segs.size(); si++) {
+            const Segment& sg = lp->segs[si];
+            LaunchPlan::F32Shape& sh = lp->f_shape[si][j];
+            sh = LaunchPlan::F32Shape();
+            int64_t B = -1;
+            for (int s = 0; s < sg.n_fd; s++) {
+                const int64_t Bs = sg.fd[s].bin == 0 ? b.nchan : sg.fd[s].bin;
+                B = (B == -1 || B == Bs) ? Bs : 0;
+            }
+            const int64_t nbins = B > 0 ? b.nchan / B : 0;
+            const bool fast = sg.n_fd > 0 && (B == 8 || B == 16 || B == 32 || B == 64) &&
+                              nbins <= (B == 64 ? 64 : 128);
+            if (fast) {
+                const int32_t Cp = (int32_t)(nbins * (B + 4));
+                const size_t per = (size_t)Cp * 4 + (b.flags ? (size_t)b.nchan : 0);
+                int t = 4;
+                while (t * 2 <= lp->tune.f32_tile_cap && t < 64) t *= 2;
+                while (t > 4 && per * t > budget) t >>= 1;
+                if (per * t <= lds_limit()) {
+                    sh.B = (int32_t)B;
+                    sh.bpl = nbins > 64 ? 2 : 1;
+                    sh.Cp = Cp;
+                    sh.Tt = t;
+                    sh.lds = per * t;
+                }
+            }
+        }
+    }
+    return RFIM_OK;
+}
+
 rfim_status make_launch_plan(const rfim_beam* beams, int32_t nbeams, const rfim_step* steps,
-                             int32_t nsteps, bool want_counts, LaunchPlan* lp) {
+                             int32_t nsteps, bool want_counts, const TuneParams& tune, LaunchPlan* lp) {
+    lp->tune = tune;
     lp->segs = segments_of(steps, nsteps);
     lp->nsteps = nsteps;
     lp->Tt.assign(nbeams, 0);
@@ -383,41 +440,25 @@ rfim_status make_launch_plan(const rfim_beam* beams, int32_t nbeams, const rfim_
             continue;
         }
         lp->u8_beams.push_back(i);
-        if (!tile_shape(b, b.flags != nullptr, &lp->Tt[i], &lp->Cp[i])) return RFIM_ERR_UNSUPPORTED;
+        if (!tile_shape_u8(b, b.flags != nullptr, tune.u8_tile_cap, &lp->Tt[i], &lp->Cp[i]))
+            return RFIM_ERR_UNSUPPORTED;
         lp->u8_rows += b.nchan;
         lp->u8_tiles += (b.nsamp + lp->Tt[i] - 1) / lp->Tt[i];
         size_t lds = (size_t)lp->Tt[i] * lp->Cp[i] * (b.flags ? 2 : 1);
         lp->u8_lds = std::max(lp->u8_lds, lds);
     }
-    if (!lp->f32_beams.empty()) return RFIM_ERR_UNSUPPORTED;
     if (lp->u8_rows >= ((int64_t)1 << 31) || lp->u8_tiles >= ((int64_t)1 << 31))
         return RFIM_ERR_UNSUPPORTED;
-    {
-        static const size_t chunk_bytes = [] {
-            // off by default: measured slower on the 40-beam workload (3.1 vs
-            // 1.5 ms per step) because the small per-chunk launches lose more
-            // than the cache reuse gains
-            const char* e = std::getenv("RFIM_CHUNK_MB");
-            long v = e ? std::atol(e) : 0;
-            return (size_t)(v > 0 ? v : 0) << 20;
-        }();
-        size_t acc = 0;
-        lp->chunk_begin.clear();
-        lp->chunk_begin.push_back(0);
-        for (int j = 0; j < (int)lp->u8_beams.size(); j++) {
-            const rfim_beam& b = beams[lp->u8_beams[j]];
-            const size_t bytes = (size_t)b.nchan * (size_t)b.nsamp;
-            if (chunk_bytes && acc > 0 && acc + bytes > chunk_bytes) {
-                lp->chunk_begin.push_back(j);
-                acc = 0;
-            }
-            acc += bytes;
-        }
-        lp->chunk_begin.push_back((int)lp->u8_beams.size());
-    }
-    lp->rec_bytes = (size_t)lp->u8_rows * std::max(1, lp->max_td) * 4;
-    lp->rec_bytes = (lp->rec_bytes + 255) & ~(size_t)255;
-    lp->count_bytes = want_counts ? (size_t)nbeams * 8 * sizeof(unsigned long long) : 0;
+    rfim_status fs = plan_f32(beams, lp);
+    if (fs != RFIM_OK) return fs;
+    auto al = [](size_t v) { return (v + 255) & ~(size_t)255; };
+    lp->count_bytes = want_counts ? al((size_t)nbeams * 8 * sizeof(unsigned long long)) : 0;
+    lp->off_u8rec = lp->count_bytes;
+    lp->off_f32rec = lp->off_u8rec + al((size_t)lp->u8_rows * std::max(1, lp->max_td) * 4);
+    lp->off_wide = lp->off_f32rec + al((size_t)lp->f32_rows * std::max(1, lp->max_td) * 16);
+    lp->off_tditems = lp->off_wide + (lp->f32_beams.empty() ? 0 : 256);
+    lp->off_fditems = lp->off_tditems + al((size_t)lp->f32_rows * 8);
+    lp->work_bytes = lp->off_fditems + al((size_t)lp->f32_cols * 8);
     return RFIM_OK;
 }
 
@@ -428,108 +469,315 @@ rfim_status dev_err(hipError_t e) {
     return e == hipSuccess ? RFIM_OK : RFIM_ERR_DEVICE;
 }
 
-// Enqueue a whole step list.  counts (device, nullable): [nbeams][8].
+// ---------------------------------------------------------------------------
+// The launch program of a call: every beam table of the call in one blob and
+// the ordered kernel launches that read them.  Built on the host per call (or
+// once for a captured graph), then enqueued on one stream.
+// ---------------------------------------------------------------------------
+enum Op {
+    OP_ZERO_COUNTS, OP_TD_U8, OP_FUSED_U8, OP_ZERO_WIDE, OP_TD_F32, OP_LIST_ALL, OP_TD_WIDE,
+    OP_FUSED_F32, OP_FD_WIDE
+};
+
+struct Launch {
+    int op = 0;
+    int seg = -1;       // index into Program::segs
+    int table = -1;     // first DevBeam of its table in the blob
+    int nbeams = 0;
+    int64_t total = 0;  // rows / tiles / list length
+    int a = 0, b = 0;   // TD f32 (nt, vpt); fused f32 (B, bpl); wide (grid); list (gidx)
+    size_t lds = 0;
+    bool vec = false;
+};
+
+struct Program {
+    std::vector<DevBeam> blob;
+    std::vector<Segment> segs;
+    std::vector<Launch> launches;
+};
+
+DevBeam dev_beam(const rfim_beam& b, bool first_seg) {
+    DevBeam d;
+    std::memset(&d, 0, sizeof(d));
+    d.in = first_seg ? b.in : b.out;
+    d.out = b.out;
+    d.flags = b.flags;
+    d.C = b.nchan;
+    d.T = b.nsamp;
+    d.stride = b.row_stride;
+    return d;
+}
+
+void build_u8(const rfim_beam* beams, const LaunchPlan& lp, Program& pg) {
+    const int nu8 = (int)lp.u8_beams.size();
+    if (nu8 == 0) return;
+    for (size_t si = 0; si < lp.segs.size(); si++) {
+        Segment seg = lp.segs[si];
+        bool any_flags = false;
+        for (int j = 0; j < nu8; j++) any_flags |= beams[lp.u8_beams[j]].flags != nullptr;
+        seg.flags_mode = any_flags ? (si == 0 ? 1 : 2) : 0;
+        const int sidx = (int)pg.segs.size();
+        pg.segs.push_back(seg);
+        const int table = (int)pg.blob.size();
+        int64_t row = 0, tile = 0;
+        for (int j = 0; j < nu8; j++) {
+            const int bi = lp.u8_beams[j];
+            DevBeam d = dev_beam(beams[bi], si == 0);
+            d.row0 = row;
+            d.rec0 = row;
+            d.tile0 = tile;
+            d.Tt = lp.Tt[bi];
+            d.Cp = lp.Cp[bi];
+            d.cidx = bi;
+            row += d.C;
+            tile += (d.T + d.Tt - 1) / d.Tt;
+            pg.blob.push_back(d);
+        }
+        if (seg.n_td > 0) {
+            Launch L;
+            L.op = OP_TD_U8;
+            L.seg = sidx;
+            L.table = table;
+            L.nbeams = nu8;
+            L.total = row;
+            pg.launches.push_back(L);
+        }
+        Launch L;
+        L.op = OP_FUSED_U8;
+        L.seg = sidx;
+        L.table = table;
+        L.nbeams = nu8;
+        L.total = tile;
+        L.lds = lp.u8_lds;
+        L.vec = fd_vec_ok(beams, lp, seg);
+        pg.launches.push_back(L);
+    }
+}
+
+// float32 beams: per run of [TD][FD] steps, TD rows (register-resident kernel
+// per row-length class, wide fallback for the rows it lists), then the fused
+// TD-apply + FD pass per bin class and the wide fallback for the time samples
+// it lists.
+void build_f32(const rfim_beam* beams, const LaunchPlan& lp, Program& pg) {
+    const int nf = (int)lp.f32_beams.size();
+    if (nf == 0) return;
+    static const int td_shapes[7][2] = {{256, 1}, {256, 4}, {256, 16}, {1024, 8}, {1024, 16}, {1024, 32}, {1024, 64}};
+    static const int fd_shapes[8][2] = {{0, 1}, {8, 1}, {8, 2}, {16, 1}, {16, 2}, {32, 1}, {32, 2}, {64, 1}};
+    for (size_t si = 0; si < lp.segs.size(); si++) {
+        Segment seg = lp.segs[si];
+        bool any_flags = false;
+        for (int j = 0; j < nf; j++) any_flags |= beams[lp.f32_beams[j]].flags != nullptr;
+        seg.flags_mode = any_flags ? (si == 0 ? 1 : 2) : 0;
+        const int sidx = (int)pg.segs.size();
+        pg.segs.push_back(seg);
+        // table of every float32 beam (the wide kernels index it)
+        const int all = (int)pg.blob.size();
+        int64_t rows = 0, cols = 0;
+        for (int j = 0; j < nf; j++) {
+            DevBeam d = dev_beam(beams[lp.f32_beams[j]], si == 0);
+            d.rec0 = rows;
+            d.cidx = lp.f32_beams[j];
+            d.pad = j;
+            rows += d.C;
+            cols += d.T;
+            pg.blob.push_back(d);
+        }
+        Launch Z;
+        Z.op = OP_ZERO_WIDE;
+        Z.seg = sidx;
+        pg.launches.push_back(Z);
+        if (seg.n_td > 0) {
+            for (auto& sh : td_shapes) {
+                const int table = (int)pg.blob.size();
+                int64_t row = 0;
+                int n = 0;
+                for (int j = 0; j < nf; j++) {
+                    if (lp.f_nt[j] != sh[0] || lp.f_vpt[j] != sh[1]) continue;
+                    DevBeam d = pg.blob[all + j];
+                    d.row0 = row;
+                    row += d.C;
+                    pg.blob.push_back(d);
+                    n++;
+                }
+                if (!n) continue;
+                Launch L;
+                L.op = OP_TD_F32;
+                L.seg = sidx;
+                L.table = table;
+                L.nbeams = n;
+                L.total = row;
+                L.a = sh[0];
+                L.b = sh[1];
+                pg.launches.push_back(L);
+            }
+            for (int j = 0; j < nf; j++) {
+                if (lp.f_nt[j] != 0) continue;
+                Launch L;
+                L.op = OP_LIST_ALL;
+                L.seg = sidx;
+                L.total = pg.blob[all + j].C;
+                L.a = j;
+                L.b = 0;   // the TD list
+                pg.launches.push_back(L);
+            }
+            Launch W;
+            W.op = OP_TD_WIDE;
+            W.seg = sidx;
+            W.table = all;
+            W.nbeams = nf;
+            W.a = (int)std::min<int64_t>(rows, 512);
+            pg.launches.push_back(W);
+        }
+        for (auto& fsh : fd_shapes) {
+            const int table = (int)pg.blob.size();
+            int64_t tile = 0;
+            size_t lds = 0;
+            int n = 0;
+            for (int j = 0; j < nf; j++) {
+                const LaunchPlan::F32Shape& sh = lp.f_shape[si][j];
+                if (sh.B != fsh[0] || (sh.B && sh.bpl != fsh[1])) continue;
+                DevBeam d = pg.blob[all + j];
+                d.tile0 = tile;
+                d.Tt = sh.Tt;
+                d.Cp = sh.Cp;
+                tile += (d.T + sh.Tt - 1) / sh.Tt;
+                lds = std::max(lds, sh.lds);
+                pg.blob.push_back(d);
+                n++;
+            }
+            if (!n) continue;
+            Launch L;
+            L.op = OP_FUSED_F32;
+            L.seg = sidx;
+            L.table = table;
+            L.nbeams = n;
+            L.total = tile;
+            L.a = fsh[0];
+            L.b = fsh[1];
+            L.lds = lds;
+            pg.launches.push_back(L);
+        }
+        if (seg.n_fd > 0) {
+            Launch W;
+            W.op = OP_FD_WIDE;
+            W.seg = sidx;
+            W.table = all;
+            W.nbeams = nf;
+            W.a = (int)std::min<int64_t>(cols, 512);
+            pg.launches.push_back(W);
+        }
+    }
+}
+
+void build_program(const rfim_beam* beams, int32_t nbeams, const LaunchPlan& lp, bool want_counts, Program& pg) {
+    pg = Program();
+    if (want_counts) {
+        Launch Z;
+        Z.op = OP_ZERO_COUNTS;
+        Z.total = (int64_t)nbeams * 8;
+        pg.launches.push_back(Z);
+    }
+    build_u8(beams, lp, pg);
+    build_f32(beams, lp, pg);
+}
+
+// Enqueues the program on `stream`; d_blob is the device copy of pg.blob.
+rfim_status enqueue(const Program& pg, const LaunchPlan& lp, const DevBeam* d_blob, Workspace& ws,
+                    hipStream_t stream, bool want_counts) {
+    char* wbase = (char*)ws.d_work;
+    uint32_t* u8rec = (uint32_t*)(wbase + lp.off_u8rec);
+    unsigned long long* counts = want_counts ? (unsigned long long*)wbase : nullptr;
+    float4* frec = (float4*)(wbase + lp.off_f32rec);
+    unsigned* wide_td_n = (unsigned*)(wbase + lp.off_wide);
+    unsigned* wide_fd_n = (unsigned*)(wbase + lp.off_wide + 8);
+    int2* td_items = (int2*)(wbase + lp.off_tditems);
+    int2* fd_items = (int2*)(wbase + lp.off_fditems);
+    for (const Launch& L : pg.launches) {
+        const DevBeam* tab = L.table >= 0 ? d_blob + L.table : nullptr;
+        const Segment& seg = pg.segs[L.seg >= 0 ? L.seg : 0];
+        hipError_t e = hipSuccess;
+        switch (L.op) {
+            case OP_ZERO_COUNTS:
+                e = launch_zero_u64(counts, L.total, stream);
+                break;
+            case OP_TD_U8:
+                e = ws.timed_launch(RFIM_KERNEL_TD_ROWS_U8, stream, [&] {
+                    return launch_td_rows_u8(tab, L.nbeams, L.total, seg, u8rec, counts, 8, stream);
+                });
+                break;
+            case OP_FUSED_U8:
+                e = ws.timed_launch(RFIM_KERNEL_FUSED_U8, stream, [&] {
+                    return launch_fused_u8(tab, L.nbeams, L.total, seg, u8rec, L.lds, L.vec, counts, 8, stream);
+                });
+                break;
+            case OP_ZERO_WIDE:
+                e = launch_zero_u64((unsigned long long*)wide_td_n, 2, stream);
+                break;
+            case OP_TD_F32:
+                e = ws.timed_launch(RFIM_KERNEL_TD_ROWS_F32, stream, [&] {
+                    return launch_td_rows_f32(tab, L.nbeams, L.total, L.a, L.b, seg, frec, wide_td_n, td_items,
+                                              counts, 8, stream);
+                });
+                break;
+            case OP_LIST_ALL:
+                e = launch_list_all(L.b ? wide_fd_n : wide_td_n, L.b ? fd_items : td_items, L.a, L.total, stream);
+                break;
+            case OP_TD_WIDE:
+                e = ws.timed_launch(RFIM_KERNEL_TD_WIDE_F32, stream, [&] {
+                    return launch_td_wide_f32(tab, wide_td_n, td_items, L.a, seg, frec, counts, 8, stream);
+                });
+                break;
+            case OP_FUSED_F32:
+                e = ws.timed_launch(RFIM_KERNEL_FUSED_F32, stream, [&] {
+                    return launch_fused_f32(tab, L.nbeams, L.total, L.a, L.b, seg, frec, L.lds, wide_fd_n,
+                                            fd_items, counts, 8, stream);
+                });
+                break;
+            case OP_FD_WIDE:
+                e = ws.timed_launch(RFIM_KERNEL_FD_WIDE_F32, stream, [&] {
+                    return launch_fd_wide_f32(tab, wide_fd_n, fd_items, L.a, lp.f32_maxC, seg, counts, 8, stream);
+                });
+                break;
+        }
+        if (e != hipSuccess) return dev_err(e);
+    }
+    return RFIM_OK;
+}
+
+// Builds and enqueues a whole step list, staging the beam tables through the
+// workspace ring in one copy.
 rfim_status execute(const rfim_beam* beams, int32_t nbeams, const LaunchPlan& lp, Workspace& ws,
                     hipStream_t stream, bool want_counts) {
     if (ws.has_last && ws.last_stream != stream) {
         // the shared workspace may still be in use by a call on another stream
         if (hipStreamWaitEvent(stream, ws.last_done, 0) != hipSuccess) return RFIM_ERR_DEVICE;
     }
-    rfim_status st = ws.reserve_work(lp.rec_bytes + lp.count_bytes);
+    rfim_status st = ws.reserve_work(lp.work_bytes);
     if (st != RFIM_OK) return st;
-    uint32_t* d_rec = (uint32_t*)ws.d_work;
-    unsigned long long* d_counts =
-        want_counts ? (unsigned long long*)((char*)ws.d_work + lp.rec_bytes) : nullptr;
-    if (d_counts) {
-        st = dev_err(launch_zero_u64(d_counts, (int64_t)nbeams * 8, stream));
-        if (st != RFIM_OK) return st;
-    }
-    const int nu8 = (int)lp.u8_beams.size();
-    const int nchunks = (int)lp.chunk_begin.size() - 1;
-    for (size_t si = 0; si < lp.segs.size() && nu8 > 0; si++) {
-        Segment seg = lp.segs[si];
-        bool any_flags = false;
-        for (int j = 0; j < nu8; j++) any_flags |= beams[lp.u8_beams[j]].flags != nullptr;
-        seg.flags_mode = any_flags ? (si == 0 ? 1 : 2) : 0;
-        const bool chunked = seg.n_td > 0 && nchunks > 1;
-        hipStream_t ts = stream;   // stream of the row-statistics kernels
-        if (chunked) {
-            st = ws.chunk_resources(1 + 2 * (size_t)nchunks);
-            if (st != RFIM_OK) return st;
-            ts = ws.aux;
-            // fork: the aux stream starts after everything already on `stream`
-            if (hipEventRecord(ws.chunk_ev[0], stream) != hipSuccess ||
-                hipStreamWaitEvent(ts, ws.chunk_ev[0], 0) != hipSuccess)
-                return RFIM_ERR_DEVICE;
-        }
-        const int nparts = chunked ? nchunks : 1;
-        int64_t row_base = 0;
-        for (int ci = 0; ci < nparts; ci++) {
-            const int jb = chunked ? lp.chunk_begin[ci] : 0, je = chunked ? lp.chunk_begin[ci + 1] : nu8;
-            const int nt = je - jb;
-            std::vector<DevBeam> tab(nt);
-            int64_t row = 0, tile = 0;
-            for (int j = 0; j < nt; j++) {
-                const int bi = lp.u8_beams[jb + j];
-                const rfim_beam& b = beams[bi];
-                DevBeam& d = tab[j];
-                d.in = si == 0 ? b.in : b.out;
-                d.out = b.out;
-                d.flags = b.flags;
-                d.C = b.nchan;
-                d.T = b.nsamp;
-                d.stride = b.row_stride;
-                d.row0 = row;
-                d.tile0 = tile;
-                d.Tt = lp.Tt[bi];
-                d.Cp = lp.Cp[bi];
-                d.cidx = bi;
-                d.pad = 0;
-                row += b.nchan;
-                tile += (b.nsamp + d.Tt - 1) / d.Tt;
-            }
-            Slot* sl = nullptr;
-            const size_t bytes = sizeof(DevBeam) * (size_t)nt;
-            st = ws.slot(bytes, &sl);
-            if (st != RFIM_OK) return st;
-            std::memcpy(sl->h, tab.data(), bytes);
-            if (chunked && ci >= 2) {
-                // keep the statistics at most two chunks ahead of the fused
-                // pass, so the chunk it reads is still cached
-                if (hipStreamWaitEvent(ts, ws.chunk_ev[1 + 2 * (ci - 2) + 1], 0) != hipSuccess)
-                    return RFIM_ERR_DEVICE;
-            }
-            st = dev_err(hipMemcpyAsync(sl->d, sl->h, bytes, hipMemcpyHostToDevice, ts));
-            if (st != RFIM_OK) return st;
-            const DevBeam* d_tab = (const DevBeam*)sl->d;
-            uint32_t* rec = d_rec + row_base * std::max(1, seg.n_td);
-            if (seg.n_td > 0) {
-                st = dev_err(ws.timed_launch(RFIM_KERNEL_TD_ROWS_U8, ts, [&] {
-                    return launch_td_rows_u8(d_tab, nt, row, seg, rec, d_counts, 8, ts);
-                }));
-                if (st != RFIM_OK) return st;
-            }
-            if (chunked) {
-                hipEvent_t td_done = ws.chunk_ev[1 + 2 * ci];
-                if (hipEventRecord(td_done, ts) != hipSuccess || hipStreamWaitEvent(stream, td_done, 0) != hipSuccess)
-                    return RFIM_ERR_DEVICE;
-            }
-            const bool vec = fd_vec_ok(beams, lp, seg);
-            st = dev_err(ws.timed_launch(RFIM_KERNEL_FUSED_U8, stream, [&] {
-                return launch_fused_u8(d_tab, nt, tile, seg, rec, lp.u8_lds, vec, d_counts, 8, stream);
-            }));
-            if (st != RFIM_OK) return st;
-            if (chunked && hipEventRecord(ws.chunk_ev[1 + 2 * ci + 1], stream) != hipSuccess)
-                return RFIM_ERR_DEVICE;
-            if (hipEventRecord(sl->ev, stream) != hipSuccess) return RFIM_ERR_DEVICE;
-            sl->used = true;
-            row_base += row;
-        }
-    }
+    Program pg;
+    build_program(beams, nbeams, lp, want_counts, pg);
+    Slot* sl = nullptr;
+    const size_t bytes = sizeof(DevBeam) * std::max<size_t>(1, pg.blob.size());
+    st = ws.slot(bytes, &sl);
+    if (st != RFIM_OK) return st;
+    std::memcpy(sl->h, pg.blob.data(), sizeof(DevBeam) * pg.blob.size());
+    if (hipMemcpyAsync(sl->d, sl->h, bytes, hipMemcpyHostToDevice, stream) != hipSuccess) return RFIM_ERR_DEVICE;
+    st = enqueue(pg, lp, (const DevBeam*)sl->d, ws, stream, want_counts);
+    if (st != RFIM_OK) return st;
+    if (hipEventRecord(sl->ev, stream) != hipSuccess) return RFIM_ERR_DEVICE;
+    sl->used = true;
     if (hipEventRecord(ws.last_done, stream) != hipSuccess) return RFIM_ERR_DEVICE;
     ws.last_stream = stream;
     ws.has_last = true;
     return RFIM_OK;
+}
+
+// Number of DevBeam entries the program of these shapes uses (plans size
+// their staging slots with it).
+size_t program_entries(const rfim_beam* beams, int32_t nbeams, const LaunchPlan& lp) {
+    Program pg;
+    build_program(beams, nbeams, lp, true, pg);
+    return pg.blob.size();
 }
 
 }  // namespace
@@ -543,7 +791,39 @@ struct rfim_plan {
     std::vector<rfim_step> steps;
     LaunchPlan lp;
     Workspace ws;
+    // captured graph of one run with fixed buffers
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    void* d_blob = nullptr;
+
+    ~rfim_plan() {
+        if (ws.has_last) (void)hipEventSynchronize(ws.last_done);
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (d_blob) (void)hipFree(d_blob);
+    }
 };
+
+namespace {
+
+rfim_status check_plan_match(const rfim_plan* plan, const rfim_beam* beams, int32_t nbeams,
+                             const rfim_step* steps, int32_t nsteps) {
+    if ((int32_t)plan->shapes.size() != nbeams || (int32_t)plan->steps.size() != nsteps)
+        return RFIM_ERR_INVALID_ARG;
+    for (int i = 0; i < nbeams; i++) {
+        const rfim_beam &a = beams[i], &p = plan->shapes[i];
+        if (a.dtype != p.dtype || a.nchan != p.nchan || a.nsamp != p.nsamp || a.row_stride != p.row_stride ||
+            (a.flags == nullptr) != (p.flags == nullptr))
+            return RFIM_ERR_INVALID_ARG;
+    }
+    if (nsteps && std::memcmp(steps, plan->steps.data(), sizeof(rfim_step) * (size_t)nsteps) != 0)
+        return RFIM_ERR_INVALID_ARG;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev != plan->device) return RFIM_ERR_INVALID_ARG;
+    return RFIM_OK;
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -559,7 +839,7 @@ const char* rfim_status_string(rfim_status s) {
     return "unknown status";
 }
 
-const char* rfim_version(void) { return "0.1.0"; }
+const char* rfim_version(void) { return "0.2.0"; }
 
 rfim_status rfim_pipeline_run(const rfim_beam* beams, int32_t nbeams, const rfim_step* steps,
                               int32_t nsteps, rfim_plan* plan, void* stream) {
@@ -582,23 +862,13 @@ rfim_status rfim_pipeline_run(const rfim_beam* beams, int32_t nbeams, const rfim
         return RFIM_OK;
     }
     if (plan) {
-        if ((int32_t)plan->shapes.size() != nbeams || (int32_t)plan->steps.size() != nsteps)
-            return RFIM_ERR_INVALID_ARG;
-        for (int i = 0; i < nbeams; i++) {
-            const rfim_beam &a = beams[i], &p = plan->shapes[i];
-            if (a.dtype != p.dtype || a.nchan != p.nchan || a.nsamp != p.nsamp ||
-                a.row_stride != p.row_stride || (a.flags == nullptr) != (p.flags == nullptr))
-                return RFIM_ERR_INVALID_ARG;
-        }
-        if (std::memcmp(steps, plan->steps.data(), sizeof(rfim_step) * (size_t)nsteps) != 0)
-            return RFIM_ERR_INVALID_ARG;
-        int dev = 0;
-        if (hipGetDevice(&dev) != hipSuccess || dev != plan->device) return RFIM_ERR_INVALID_ARG;
+        st = check_plan_match(plan, beams, nbeams, steps, nsteps);
+        if (st != RFIM_OK) return st;
         std::lock_guard<std::mutex> lk(plan->ws.mu);
         return execute(beams, nbeams, plan->lp, plan->ws, (hipStream_t)stream, true);
     }
     LaunchPlan lp;
-    st = make_launch_plan(beams, nbeams, steps, nsteps, false, &lp);
+    st = make_launch_plan(beams, nbeams, steps, nsteps, false, default_tune(), &lp);
     if (st != RFIM_OK) return st;
     Workspace* ws = nullptr;
     st = device_workspace(&ws);
@@ -619,17 +889,19 @@ rfim_status rfim_fd_sigma_cut(const rfim_beam* beams, int32_t nbeams, double k, 
     return rfim_pipeline_run(beams, nbeams, &s, 1, nullptr, stream);
 }
 
-rfim_status rfim_plan_create(const rfim_beam* shapes, int32_t nbeams, const rfim_step* steps,
-                             int32_t nsteps, const char* tune_cache_path, rfim_plan** out) {
-    (void)tune_cache_path;
+}  // extern "C"
+
+namespace rfim {
+
+// a plan with explicit tuning parameters (the autotuner times candidates)
+rfim_status plan_create_tuned(const rfim_beam* shapes, int32_t nbeams, const rfim_step* steps, int32_t nsteps,
+                              const TuneParams& tune, rfim_plan** out) {
     if (!out) return RFIM_ERR_INVALID_ARG;
     *out = nullptr;
     if (nbeams < 1 || nsteps < 1) return RFIM_ERR_INVALID_ARG;
     // shape-only validation: pointers are not dereferenced, use dummies
     std::vector<rfim_beam> tmp(shapes, shapes + nbeams);
-    for (auto& b : tmp) {
-        b.in = b.out = (void*)(uintptr_t)4096;
-    }
+    for (auto& b : tmp) b.in = b.out = (void*)(uintptr_t)4096;
     rfim_status st = validate(tmp.data(), nbeams, steps, nsteps);
     if (st != RFIM_OK) return st;
     rfim_plan* p = new (std::nothrow) rfim_plan();
@@ -640,12 +912,12 @@ rfim_status rfim_plan_create(const rfim_beam* shapes, int32_t nbeams, const rfim
     }
     p->shapes.assign(shapes, shapes + nbeams);
     p->steps.assign(steps, steps + nsteps);
-    st = make_launch_plan(shapes, nbeams, steps, nsteps, true, &p->lp);
+    st = make_launch_plan(shapes, nbeams, steps, nsteps, true, tune, &p->lp);
     if (st == RFIM_OK) st = p->ws.init(p->device);
-    if (st == RFIM_OK) st = p->ws.reserve_work(p->lp.rec_bytes + p->lp.count_bytes);
+    if (st == RFIM_OK) st = p->ws.reserve_work(p->lp.work_bytes);
     if (st == RFIM_OK) {
         // pre-size every staging slot for the beam tables of this plan
-        size_t bytes = sizeof(DevBeam) * (size_t)std::max<size_t>(1, nbeams);
+        size_t bytes = sizeof(DevBeam) * std::max<size_t>(1, program_entries(shapes, nbeams, p->lp));
         for (int i = 0; i < kRing && st == RFIM_OK; i++) {
             Slot* sl = nullptr;
             st = p->ws.slot(bytes, &sl);
@@ -661,9 +933,90 @@ rfim_status rfim_plan_create(const rfim_beam* shapes, int32_t nbeams, const rfim
     return RFIM_OK;
 }
 
+}  // namespace rfim
+
+extern "C" {
+
+rfim_status rfim_plan_create(const rfim_beam* shapes, int32_t nbeams, const rfim_step* steps,
+                             int32_t nsteps, const char* tune_cache_path, rfim_plan** out) {
+    if (!out) return RFIM_ERR_INVALID_ARG;
+    *out = nullptr;
+    TuneParams tune = default_tune();
+    if (tune_cache_path && *tune_cache_path && nbeams > 0 && shapes && nsteps > 0 && steps) {
+        const rfim_status st = tune_cache_lookup(tune_cache_path, shapes, nbeams, steps, nsteps, &tune);
+        if (st != RFIM_OK && st != RFIM_ERR_UNSUPPORTED) return st;   // UNSUPPORTED: no entry yet
+    }
+    return plan_create_tuned(shapes, nbeams, steps, nsteps, tune, out);
+}
+
 rfim_status rfim_plan_destroy(rfim_plan* plan) {
     if (!plan) return RFIM_ERR_INVALID_ARG;
     delete plan;
+    return RFIM_OK;
+}
+
+rfim_status rfim_plan_capture(rfim_plan* plan, const rfim_beam* beams, int32_t nbeams, void* stream) {
+    if (!plan) return RFIM_ERR_INVALID_ARG;
+    std::vector<rfim_step> steps = plan->steps;
+    rfim_status st = validate(beams, nbeams, steps.data(), (int32_t)steps.size());
+    if (st != RFIM_OK) return st;
+    st = check_plan_match(plan, beams, nbeams, steps.data(), (int32_t)steps.size());
+    if (st != RFIM_OK) return st;
+    std::lock_guard<std::mutex> lk(plan->ws.mu);
+    Workspace& ws = plan->ws;
+    if (ws.has_last && hipEventSynchronize(ws.last_done) != hipSuccess) return RFIM_ERR_DEVICE;
+    if (plan->exec) (void)hipGraphExecDestroy(plan->exec);
+    if (plan->graph) (void)hipGraphDestroy(plan->graph);
+    if (plan->d_blob) (void)hipFree(plan->d_blob);
+    plan->exec = nullptr;
+    plan->graph = nullptr;
+    plan->d_blob = nullptr;
+    Program pg;
+    build_program(beams, nbeams, plan->lp, true, pg);
+    // the graph reads its beam tables from plan-owned device memory written
+    // once here: replays carry no copies or memsets
+    const size_t bytes = sizeof(DevBeam) * std::max<size_t>(1, pg.blob.size());
+    if (hipMalloc(&plan->d_blob, bytes) != hipSuccess) return RFIM_ERR_OUT_OF_MEMORY;
+    if (hipMemcpy(plan->d_blob, pg.blob.data(), sizeof(DevBeam) * pg.blob.size(), hipMemcpyHostToDevice) !=
+        hipSuccess)
+        return RFIM_ERR_DEVICE;
+    const bool timing = ws.timing;
+    ws.timing = false;   // no timing events inside a graph
+    hipStream_t s = (hipStream_t)stream;
+    if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        ws.timing = timing;
+        return RFIM_ERR_DEVICE;
+    }
+    st = enqueue(pg, plan->lp, (const DevBeam*)plan->d_blob, ws, s, true);
+    hipGraph_t g = nullptr;
+    const hipError_t ec = hipStreamEndCapture(s, &g);
+    ws.timing = timing;
+    if (st != RFIM_OK || ec != hipSuccess || !g) {
+        if (g) (void)hipGraphDestroy(g);
+        return st != RFIM_OK ? st : RFIM_ERR_DEVICE;
+    }
+    hipGraphExec_t ex = nullptr;
+    if (hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        return RFIM_ERR_DEVICE;
+    }
+    plan->graph = g;
+    plan->exec = ex;
+    return RFIM_OK;
+}
+
+rfim_status rfim_plan_replay(rfim_plan* plan, void* stream) {
+    if (!plan) return RFIM_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(plan->ws.mu);
+    if (!plan->exec) return RFIM_ERR_INVALID_ARG;
+    Workspace& ws = plan->ws;
+    hipStream_t s = (hipStream_t)stream;
+    if (ws.has_last && ws.last_stream != s && hipStreamWaitEvent(s, ws.last_done, 0) != hipSuccess)
+        return RFIM_ERR_DEVICE;
+    if (hipGraphLaunch(plan->exec, s) != hipSuccess) return RFIM_ERR_DEVICE;
+    if (hipEventRecord(ws.last_done, s) != hipSuccess) return RFIM_ERR_DEVICE;
+    ws.last_stream = s;
+    ws.has_last = true;
     return RFIM_OK;
 }
 
@@ -678,8 +1031,7 @@ rfim_status rfim_plan_flag_counts(const rfim_plan* plan, uint64_t* host_out) {
     }
     if (hipEventSynchronize(p->ws.last_done) != hipSuccess) return RFIM_ERR_DEVICE;
     std::vector<unsigned long long> tmp((size_t)nb * 8);
-    if (hipMemcpy(tmp.data(), (char*)p->ws.d_work + p->lp.rec_bytes, tmp.size() * 8,
-                  hipMemcpyDeviceToHost) != hipSuccess)
+    if (hipMemcpy(tmp.data(), (char*)p->ws.d_work, tmp.size() * 8, hipMemcpyDeviceToHost) != hipSuccess)
         return RFIM_ERR_DEVICE;
     for (int b = 0; b < nb; b++)
         for (int s = 0; s < ns; s++) host_out[(size_t)b * ns + s] = s < 8 ? tmp[(size_t)b * 8 + s] : 0;

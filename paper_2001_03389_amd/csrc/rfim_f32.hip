@@ -1,0 +1,918 @@
+// float32 sigma-cut kernels for gfx950 (RFIm, arXiv:2001.03389, Section IV).
+//
+// Same two-kernel shape as the uint8 path, per run of [TD steps][FD steps]:
+//  * k_td_rows_f32 -- one work-group per channel row, the whole row resident in
+//    VGPRs (up to 64 values per lane of a 1024-lane work-group).  Exact window
+//    statistics (see rfim_f32_exact.h), every TD step of the run decided and
+//    applied in registers, one record (Lo, H, r) per step: a sample x is kept
+//    by step j iff Lo_j <= x <= H_j, else it becomes r_j.
+//  * k_fused_f32 -- one work-group per (beam, time tile).  Rows in (16-byte
+//    loads), the TD records applied on the way, tile stored in LDS as [Tt][Cp]
+//    with channels contiguous and every B-channel bin padded by 4 floats so that
+//    the lanes' 16-byte bin reads hit distinct banks.  One time sample per group
+//    of lanes, one bin per lane: exact bin sums and sums of squares, the exact
+//    cut of the time sample, per-bin float32 thresholds, replacement in
+//    registers.  The tile is written back to rows.
+// Rows and time samples that leave the window (values more than 2^-24 below
+// the largest one, or a replacement value that is) go to lists that the wide
+// kernels k_td_wide_f32 / k_fd_wide_f32 finish with big integers.
+#include "rfim_big.h"
+#include "rfim_dev.h"
+
+namespace rfim {
+
+namespace {
+
+constexpr u128 kZcap = (u128)1 << 70;   // beyond every |n*a - S| of a window row
+
+// ---- wave / group reductions --------------------------------------------
+
+__device__ inline uint32_t wave_max_u32(uint32_t v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v = max(v, (uint32_t)__shfl_xor((int)v, o, 64));
+    return v;
+}
+__device__ inline uint32_t wave_min_u32(uint32_t v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v = min(v, (uint32_t)__shfl_xor((int)v, o, 64));
+    return v;
+}
+__device__ inline uint32_t wave_add_u32(uint32_t v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += (uint32_t)__shfl_xor((int)v, o, 64);
+    return v;
+}
+__device__ inline int64_t wave_add_i64(int64_t v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+// sum of u128 over lanes xor-partnered within groups of G (power of two)
+__device__ inline u128 group_add_u128(u128 v, int G) {
+    uint64_t lo = (uint64_t)v, hi = (uint64_t)(v >> 64);
+    for (int o = 1; o < G; o <<= 1) {
+        const uint64_t olo = __shfl_xor(lo, o, 64);
+        const uint64_t ohi = __shfl_xor(hi, o, 64);
+        const uint64_t nlo = lo + olo;
+        hi = hi + ohi + (nlo < lo ? 1 : 0);
+        lo = nlo;
+    }
+    return ((u128)hi << 64) | lo;
+}
+__device__ inline uint32_t group_max_u32(uint32_t v, int G) {
+    for (int o = 1; o < G; o <<= 1) v = max(v, (uint32_t)__shfl_xor((int)v, o, 64));
+    return v;
+}
+__device__ inline uint32_t group_min_u32(uint32_t v, int G) {
+    for (int o = 1; o < G; o <<= 1) v = min(v, (uint32_t)__shfl_xor((int)v, o, 64));
+    return v;
+}
+__device__ inline uint32_t group_or_u32(uint32_t v, int G) {
+    for (int o = 1; o < G; o <<= 1) v |= (uint32_t)__shfl_xor((int)v, o, 64);
+    return v;
+}
+
+// smallest power of two >= v (v <= 64)
+__device__ inline int pow2_ceil(int v) {
+    int p = 1;
+    while (p < v) p <<= 1;
+    return p;
+}
+
+// tiny test: a non-zero value below the window of a row/column whose window
+// threshold (bits of the smallest in-window magnitude) is thr
+__device__ inline bool below_window(uint32_t bits, uint32_t thr) {
+    const uint32_t m = bits & 0x7FFFFFFFu;
+    return m != 0 && m < thr;
+}
+
+__device__ inline uint32_t window_thr(int EM) { return EM - 24 >= 1 ? (uint32_t)(EM - 24) << 23 : 0u; }
+
+// ---- work-group radix select (TD median) ---------------------------------
+
+// Key of rank `rank` (ascending totalOrder) among the keys the callback adds,
+// by four 8-bit digit rounds over per-wave LDS histograms.  All NT threads call.
+template <int NT, typename AddKeys>
+__device__ inline uint32_t wg_select_key(uint64_t rank, uint32_t* s_hist, uint32_t* s_tot, uint32_t* s_sel,
+                                         AddKeys&& add_keys) {
+    constexpr int NW = NT / 64;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    uint32_t prefix = 0, mask = 0;
+    for (int shift = 24; shift >= 0; shift -= 8) {
+        for (int i = tid; i < NW * 256; i += NT) s_hist[i] = 0;
+        __syncthreads();
+        uint32_t* h = s_hist + wave * 256;
+        add_keys([&](uint32_t k) {
+            if (((k ^ prefix) & mask) == 0) atomicAdd(&h[(k >> shift) & 255u], 1u);
+        });
+        __syncthreads();
+        uint32_t cnt = 0, incl = 0;
+        if (tid < 256) {
+            for (int w = 0; w < NW; w++) cnt += s_hist[w * 256 + tid];
+            incl = cnt;
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const uint32_t t = __shfl_up(incl, o, 64);
+                if (lane >= o) incl += t;
+            }
+            if (lane == 63) s_tot[wave] = incl;
+        }
+        __syncthreads();
+        if (tid < 256) {
+            uint32_t off = 0;
+            for (int w = 0; w < wave; w++) off += s_tot[w];
+            const uint64_t excl = (uint64_t)off + incl - cnt;
+            if (cnt && excl <= rank && rank < excl + cnt) {
+                s_sel[0] = (uint32_t)tid;
+                s_sel[1] = (uint32_t)excl;
+            }
+        }
+        __syncthreads();
+        rank -= s_sel[1];
+        prefix |= s_sel[0] << shift;
+        mask |= 255u << shift;
+        __syncthreads();
+    }
+    return prefix;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// TD: one work-group per row, row resident in registers
+// ---------------------------------------------------------------------------
+template <int NT, int VPT>
+__global__ __launch_bounds__(NT) void k_td_rows_f32(const DevBeam* __restrict__ beams, int nbeams, Segment seg,
+                                                    float4* __restrict__ rec, unsigned* __restrict__ wide_n,
+                                                    int2* __restrict__ wide_items,
+                                                    unsigned long long* __restrict__ counts, int count_stride) {
+    constexpr int NW = NT / 64;
+    __shared__ uint32_t s_hist[NW * 256];
+    __shared__ uint32_t s_tot[NW], s_sel[2];
+    __shared__ int64_t s_S[NW];
+    __shared__ uint64_t s_Q[NW][2];
+    __shared__ uint32_t s_u[NW][2];
+    __shared__ float s_dec[3];
+    __shared__ int s_bad;
+    __shared__ uint32_t s_cnt[kMaxSteps];
+
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int64_t g = blockIdx.x;
+    const int b = find_beam_by_row(beams, nbeams, g);
+    const DevBeam& bm = beams[b];
+    const int64_t c = g - bm.row0;
+    const int64_t T = bm.T;
+    const float* row = (const float*)bm.in + c * bm.stride;
+    const bool vec = (VPT % 4 == 0) && ((((uintptr_t)row) & 15) == 0);
+
+    // values of this lane: index i*NT + tid (scalar) or 4*((i/4)*NT + tid) + i%4
+    // (16-byte loads); both increase with i, so the valid ones are a prefix
+    float v[VPT];
+    int nv = 0;
+    if (vec) {
+#pragma unroll
+        for (int i4 = 0; i4 < VPT / 4; i4++) {
+            const int64_t i0 = ((int64_t)i4 * NT + tid) * 4;
+            if (i0 + 3 < T) {
+                const float4 q = *(const float4*)(row + i0);
+                v[4 * i4] = q.x;
+                v[4 * i4 + 1] = q.y;
+                v[4 * i4 + 2] = q.z;
+                v[4 * i4 + 3] = q.w;
+            } else {
+#pragma unroll
+                for (int j = 0; j < 4; j++) v[4 * i4 + j] = i0 + j < T ? row[i0 + j] : 0.0f;
+            }
+            const int64_t rem = T - i0;
+            nv += rem >= 4 ? 4 : (rem > 0 ? (int)rem : 0);
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < VPT; i++) {
+            const int64_t idx = (int64_t)i * NT + tid;
+            v[i] = idx < T ? row[idx] : 0.0f;
+            nv += idx < T ? 1 : 0;
+        }
+    }
+
+    // window of the row: largest magnitude, smallest non-zero magnitude
+    uint32_t emax = 0, tmin = 0xFFFFFFFFu;
+#pragma unroll
+    for (int i = 0; i < VPT; i++) {
+        const uint32_t bb = __float_as_uint(v[i]) & 0x7FFFFFFFu;   // padding is +0
+        emax = max(emax, bb);
+        tmin = min(tmin, bb - 1u);                                  // 0 wraps: ignored
+    }
+    emax = wave_max_u32(emax);
+    tmin = wave_min_u32(tmin);
+    if (lane == 0) {
+        s_u[wave][0] = emax;
+        s_u[wave][1] = tmin;
+    }
+    if (tid < kMaxSteps) s_cnt[tid] = 0;
+    if (tid == 0) s_bad = 0;
+    __syncthreads();
+    emax = 0;
+    tmin = 0xFFFFFFFFu;
+    for (int w = 0; w < NW; w++) {
+        emax = max(emax, s_u[w][0]);
+        tmin = min(tmin, s_u[w][1]);
+    }
+    const int EM = f32_E(emax);
+    const uint32_t thr = window_thr(EM);
+    bool bad = tmin != 0xFFFFFFFFu && tmin + 1u < thr;
+    const double sc = ldexp(1.0, 174 - EM);
+    const int e = EM - 174;
+    const uint32_t n = (uint32_t)T;
+
+    for (int j = 0; j < seg.n_td && !bad; j++) {
+        const SegStep& st = seg.td[j];
+        // exact window sums
+        int64_t S = 0;
+        u128 Q = 0;
+#pragma unroll
+        for (int i0 = 0; i0 < VPT; i0 += 32) {
+            WinAcc w{0.0, 0.0, 0.0};
+#pragma unroll
+            for (int i = i0; i < (i0 + 32 < VPT ? i0 + 32 : VPT); i++) winacc_add(w, (double)v[i] * sc);
+            S += (int64_t)w.s;
+            Q += winacc_q(w);
+        }
+        S = wave_add_i64(S);
+        Q = group_add_u128(Q, 64);
+        if (lane == 0) {
+            s_S[wave] = S;
+            s_Q[wave][0] = (uint64_t)Q;
+            s_Q[wave][1] = (uint64_t)(Q >> 64);
+        }
+        __syncthreads();
+        float med = 0.0f;
+        if (st.replace == RFIM_REPLACE_MEDIAN) {
+            const uint32_t key = wg_select_key<NT>((uint64_t)(n - 1) / 2, s_hist, s_tot, s_sel, [&](auto&& add) {
+#pragma unroll
+                for (int i = 0; i < VPT; i++)
+                    if (i < nv) add(f32_key(__float_as_uint(v[i])));
+            });
+            med = __uint_as_float(key_f32(key));
+        }
+        if (wave == 0) {
+            i128 St = 0;
+            u128 Qt = 0;
+            for (int w = 0; w < NW; w++) {
+                St += s_S[w];
+                Qt += ((u128)s_Q[w][1] << 64) | s_Q[w][0];
+            }
+            const u128 Sa = St < 0 ? (u128)(-St) : (u128)St;
+            const u128 D = (u128)n * Qt - Sa * Sa;
+            const u128 z = zmax_k2(1, D, st.kx, kZcap);
+            const float H = f32_round_ratio(St + (i128)z, n, e, kRD);
+            const float Lo = f32_round_ratio(St - (i128)z, n, e, kRU);
+            const float r = st.replace == RFIM_REPLACE_MEDIAN ? med : f32_round_ratio(St, n, e, kRN);
+            if (lane == 0) {
+                s_dec[0] = Lo;
+                s_dec[1] = H;
+                s_dec[2] = r;
+                if (below_window(__float_as_uint(r), thr)) s_bad = 1;
+                rec[(bm.rec0 + c) * seg.n_td + j] = make_float4(Lo, H, r, 0.0f);
+            }
+        }
+        __syncthreads();
+        const float Lo = s_dec[0], H = s_dec[1], r = s_dec[2];
+        bad = s_bad != 0;
+        uint32_t cnt = 0;
+#pragma unroll
+        for (int i = 0; i < VPT; i++) {
+            if (i < nv) {
+                const bool f = v[i] < Lo || v[i] > H;
+                v[i] = f ? r : v[i];
+                cnt += f ? 1u : 0u;
+            }
+        }
+        cnt = wave_add_u32(cnt);
+        if (lane == 0 && cnt) atomicAdd(&s_cnt[j], cnt);
+    }
+    __syncthreads();
+    if (bad) {
+        if (tid == 0) {
+            const unsigned slot = atomicAdd(wide_n, 1u);
+            wide_items[slot] = make_int2(bm.pad, (int)c);
+        }
+        return;
+    }
+    if (counts && tid < seg.n_td && s_cnt[tid] && seg.td[tid].bit >= 0)
+        atomicAdd(&counts[(int64_t)bm.cidx * count_stride + seg.td[tid].bit], (unsigned long long)s_cnt[tid]);
+}
+
+// ---------------------------------------------------------------------------
+// TD apply + FD steps on an LDS tile, one work-group per (beam, time tile)
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr int kF32Block = 256;
+
+struct F32Tile {
+    const float* in;
+    float* out;
+    uint8_t* flags;
+    const float4* rec;   // this beam's TD records, [row][n_td]
+    int64_t C, T, stride, t0;
+    int Tt, Cp, nt, n_td;
+};
+
+// lower median (rank (B-1)/2 in totalOrder) of B register values
+template <int B>
+__device__ inline float bin_median(const float (&x)[B]) {
+    uint32_t k[B];
+#pragma unroll
+    for (int i = 0; i < B; i++) k[i] = f32_key(__float_as_uint(x[i]));
+#pragma unroll
+    for (int size = 2; size <= B; size <<= 1) {
+#pragma unroll
+        for (int stride = size / 2; stride > 0; stride >>= 1) {
+#pragma unroll
+            for (int i = 0; i < B; i++) {
+                const int j = i ^ stride;
+                if (j > i) {
+                    const uint32_t a = k[i], bb = k[j];
+                    const bool up = (i & size) == 0;
+                    k[i] = up ? min(a, bb) : max(a, bb);
+                    k[j] = up ? max(a, bb) : min(a, bb);
+                }
+            }
+        }
+    }
+    return __uint_as_float(key_f32(k[(B - 1) / 2]));
+}
+
+// All FD steps for the time samples of this wave.  B channels per bin, BPL
+// bins per lane, groups of G2 lanes per time sample.
+template <int B, int BPL>
+__device__ void fd_fast_f32(const F32Tile& k, const Segment& seg, float* tile, uint8_t* ftile, bool want_flags,
+                            unsigned* wide_n, int2* wide_items, int gidx, uint64_t cntp[2]) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    constexpr int NW = kF32Block / 64;
+    const int nbins = (int)(k.C / B);
+    const int G2 = nbins > 64 ? 64 : pow2_ceil(nbins);
+    const int CPW = 64 / G2;
+    const int cw = lane / G2, gl = lane % G2;
+    const int ncg = (k.nt + CPW - 1) / CPW;
+    const uint32_t C = (uint32_t)k.C;
+    for (int cg = wave; cg < ncg; cg += NW) {
+        const int t = cg * CPW + cw;
+        const bool colok = t < k.nt;
+        float x[BPL][B];
+        uint32_t fw[BPL][B / 4];
+        bool act[BPL];
+#pragma unroll
+        for (int kk = 0; kk < BPL; kk++) {
+            const int bin = gl + 64 * kk;
+            act[kk] = colok && bin < nbins;
+            const float* p = tile + (size_t)(colok ? t : 0) * k.Cp + (size_t)(act[kk] ? bin : 0) * (B + 4);
+#pragma unroll
+            for (int j = 0; j < B; j += 4) {
+                const float4 q = act[kk] ? *(const float4*)(p + j) : make_float4(0.f, 0.f, 0.f, 0.f);
+                x[kk][j] = q.x;
+                x[kk][j + 1] = q.y;
+                x[kk][j + 2] = q.z;
+                x[kk][j + 3] = q.w;
+            }
+#pragma unroll
+            for (int j = 0; j < B / 4; j++) fw[kk][j] = 0;
+        }
+        // window of the time sample
+        uint32_t emax = 0, tmin = 0xFFFFFFFFu;
+#pragma unroll
+        for (int kk = 0; kk < BPL; kk++)
+#pragma unroll
+            for (int j = 0; j < B; j++) {
+                const uint32_t bb = __float_as_uint(x[kk][j]) & 0x7FFFFFFFu;
+                emax = max(emax, bb);
+                tmin = min(tmin, bb - 1u);
+            }
+        emax = group_max_u32(emax, G2);
+        tmin = group_min_u32(tmin, G2);
+        const int EM = f32_E(emax);
+        const uint32_t thr = window_thr(EM);
+        uint32_t bad = (tmin != 0xFFFFFFFFu && tmin + 1u < thr) ? 1u : 0u;
+        const double sc = ldexp(1.0, 174 - EM);
+        const int e = EM - 174;
+        uint64_t lc[2] = {0, 0};   // this time sample's counts, 16 bits per step
+        for (int s = 0; s < seg.n_fd && !bad; s++) {
+            const SegStep& st = seg.fd[s];
+            int64_t S[BPL];
+            u128 V = 0;
+#pragma unroll
+            for (int kk = 0; kk < BPL; kk++) {
+                int64_t Sb = 0;
+                u128 Qb = 0;
+#pragma unroll
+                for (int j0 = 0; j0 < B; j0 += 32) {
+                    WinAcc w{0.0, 0.0, 0.0};
+#pragma unroll
+                    for (int j = j0; j < (j0 + 32 < B ? j0 + 32 : B); j++) winacc_add(w, (double)x[kk][j] * sc);
+                    Sb += (int64_t)w.s;
+                    Qb += winacc_q(w);
+                }
+                S[kk] = Sb;
+                const u128 Sa = Sb < 0 ? (u128)(-(i128)Sb) : (u128)Sb;
+                if (act[kk]) V += (u128)B * Qb - Sa * Sa;
+            }
+            V = group_add_u128(V, G2);
+            // sum over the time sample of Z_c^2 = B * sum_b (B*Q_b - S_b^2)
+            const u128 z = zmax_k2(C, (u128)B * V, st.kx, kZcap);
+            const int bit = st.bit;
+#pragma unroll
+            for (int kk = 0; kk < BPL; kk++) {
+                if (!act[kk]) continue;
+                const float H = f32_round_ratio((i128)S[kk] + (i128)z, B, e, kRD);
+                const float Lo = f32_round_ratio((i128)S[kk] - (i128)z, B, e, kRU);
+                uint64_t fm = 0;
+#pragma unroll
+                for (int j = 0; j < B; j++) fm |= (uint64_t)(x[kk][j] < Lo || x[kk][j] > H) << j;
+                if (!fm) continue;
+                const float r = st.replace == RFIM_REPLACE_MEDIAN ? bin_median<B>(x[kk])
+                                                                  : f32_round_ratio((i128)S[kk], B, e, kRN);
+                if (below_window(__float_as_uint(r), thr)) bad = 1u;
+#pragma unroll
+                for (int j = 0; j < B; j++) {
+                    const bool f = (fm >> j) & 1;
+                    x[kk][j] = f ? r : x[kk][j];
+                    if (bit >= 0 && f) fw[kk][j / 4] |= (1u << bit) << (8 * (j % 4));
+                }
+                if (bit >= 0) lc[bit >> 2] += (uint64_t)__popcll(fm) << (16 * (bit & 3));
+            }
+            bad = group_or_u32(bad, G2);
+        }
+        if (!colok) continue;
+        if (bad) {
+            if (gl == 0) {
+                const unsigned slot = atomicAdd(wide_n, 1u);
+                wide_items[slot] = make_int2(gidx, (int)(k.t0 + t));
+            }
+            continue;
+        }
+        cntp[0] += lc[0];
+        cntp[1] += lc[1];
+#pragma unroll
+        for (int kk = 0; kk < BPL; kk++) {
+            if (!act[kk]) continue;
+            const int bin = gl + 64 * kk;
+            float* p = tile + (size_t)t * k.Cp + (size_t)bin * (B + 4);
+#pragma unroll
+            for (int j = 0; j < B; j += 4) *(float4*)(p + j) = make_float4(x[kk][j], x[kk][j + 1], x[kk][j + 2], x[kk][j + 3]);
+            if (want_flags) {
+                uint32_t* fp = (uint32_t*)(ftile + (size_t)t * k.C + (size_t)bin * B);
+#pragma unroll
+                for (int j = 0; j < B / 4; j++) fp[j] |= fw[kk][j];
+            }
+        }
+    }
+}
+
+__device__ inline int64_t phys_chan(int64_t c, int B) { return B ? c + (c / B) * 4 : c; }
+
+}  // namespace
+
+// B = bin size of the fast FD path (0: no fast FD; every time sample of a run
+// with FD steps then goes to the wide list).  BPL = bins per lane.
+template <int B, int BPL>
+__global__ __launch_bounds__(kF32Block) void k_fused_f32(const DevBeam* __restrict__ beams, int nbeams,
+                                                         int64_t total_tiles, Segment seg,
+                                                         const float4* __restrict__ rec,
+                                                         unsigned* __restrict__ wide_n, int2* __restrict__ wide_items,
+                                                         unsigned long long* __restrict__ counts, int count_stride) {
+    extern __shared__ __align__(16) uint8_t lds[];
+    __shared__ unsigned long long s_cnt[8];
+    const int tid = threadIdx.x;
+    const int64_t g = xcd_remap(blockIdx.x, total_tiles);
+    const int b = find_beam_by_tile(beams, nbeams, g);
+    const DevBeam& bm = beams[b];
+    F32Tile k;
+    k.in = (const float*)bm.in;
+    k.out = (float*)bm.out;
+    k.flags = bm.flags;
+    k.C = bm.C;
+    k.T = bm.T;
+    k.stride = bm.stride;
+    k.Tt = bm.Tt;
+    k.Cp = bm.Cp;
+    k.t0 = (g - bm.tile0) * k.Tt;
+    k.nt = (int)min((int64_t)k.Tt, k.T - k.t0);
+    k.n_td = seg.n_td;
+    k.rec = rec + bm.rec0 * seg.n_td;
+    const bool want_flags = seg.flags_mode != 0 && bm.flags != nullptr;
+    const bool or_flags = seg.flags_mode == 2;
+    const bool vec = (k.stride & 3) == 0 && (((uintptr_t)k.in | (uintptr_t)k.out) & 15) == 0;
+    float* tile = (float*)lds;
+    uint8_t* ftile = lds + (size_t)k.Tt * k.Cp * 4;
+    const int TQ = k.Tt >> 2;   // 4-sample quads per tile row
+    const int64_t nitems = k.C * TQ;
+    if (tid < 8) s_cnt[tid] = 0;
+
+    // ---- phase 1: rows in, TD records applied, into LDS (B > 0) or straight out
+    for (int64_t it = tid; it < nitems; it += kF32Block) {
+        const int64_t c = it / TQ;
+        const int q = (int)(it - c * TQ);
+        const int64_t t = k.t0 + 4 * q;
+        if (t >= k.T) continue;
+        const float* p = k.in + c * k.stride + t;
+        float x[4];
+        if (vec && t + 3 < k.T) {
+            const float4 f = *(const float4*)p;
+            x[0] = f.x;
+            x[1] = f.y;
+            x[2] = f.z;
+            x[3] = f.w;
+        } else {
+#pragma unroll
+            for (int j = 0; j < 4; j++) x[j] = t + j < k.T ? p[j] : 0.0f;
+        }
+        uint32_t fb[4] = {0u, 0u, 0u, 0u};
+        for (int j = 0; j < k.n_td; j++) {
+            const float4 r4 = k.rec[c * k.n_td + j];
+            const int bit = seg.td[j].bit;
+#pragma unroll
+            for (int u = 0; u < 4; u++) {
+                const bool f = x[u] < r4.x || x[u] > r4.y;
+                x[u] = f ? r4.z : x[u];
+                if (f && bit >= 0) fb[u] |= 1u << bit;
+            }
+        }
+        if (want_flags && or_flags) {
+            const uint8_t* fp = k.flags + c * k.stride + t;
+#pragma unroll
+            for (int u = 0; u < 4; u++)
+                if (t + u < k.T) fb[u] |= fp[u];
+        }
+        if (B > 0) {
+            const int64_t pc = phys_chan(c, B);
+#pragma unroll
+            for (int u = 0; u < 4; u++) tile[(size_t)(4 * q + u) * k.Cp + pc] = x[u];
+            if (want_flags) {
+#pragma unroll
+                for (int u = 0; u < 4; u++) ftile[(size_t)(4 * q + u) * k.C + c] = (uint8_t)fb[u];
+            }
+        } else {
+            float* op = k.out + c * k.stride + t;
+            if (vec && t + 3 < k.T) {
+                *(float4*)op = make_float4(x[0], x[1], x[2], x[3]);
+            } else {
+#pragma unroll
+                for (int u = 0; u < 4; u++)
+                    if (t + u < k.T) op[u] = x[u];
+            }
+            if (want_flags) {
+                uint8_t* fp = k.flags + c * k.stride + t;
+#pragma unroll
+                for (int u = 0; u < 4; u++)
+                    if (t + u < k.T) fp[u] = (uint8_t)fb[u];
+            }
+        }
+    }
+    if (B == 0) {
+        // no fast FD for this beam: every time sample of the tile goes wide
+        if (seg.n_fd > 0)
+            for (int t = tid; t < k.nt; t += kF32Block) {
+                const unsigned slot = atomicAdd(wide_n, 1u);
+                wide_items[slot] = make_int2(bm.pad, (int)(k.t0 + t));
+            }
+        return;
+    }
+    __syncthreads();
+
+    // ---- phase 2: FD steps
+    uint64_t cntp[2] = {0, 0};
+    if (seg.n_fd > 0) {
+        if constexpr (B > 0) fd_fast_f32<B, BPL>(k, seg, tile, ftile, want_flags, wide_n, wide_items, bm.pad, cntp);
+    }
+    __syncthreads();
+
+    // ---- phase 3: tile back to rows
+    const int64_t pcB = B;
+    for (int64_t it = tid; it < nitems; it += kF32Block) {
+        const int64_t c = it / TQ;
+        const int q = (int)(it - c * TQ);
+        const int64_t t = k.t0 + 4 * q;
+        if (t >= k.T) continue;
+        const int64_t pc = phys_chan(c, (int)pcB);
+        float x[4];
+#pragma unroll
+        for (int u = 0; u < 4; u++) x[u] = tile[(size_t)(4 * q + u) * k.Cp + pc];
+        float* op = k.out + c * k.stride + t;
+        if (vec && t + 3 < k.T) {
+            *(float4*)op = make_float4(x[0], x[1], x[2], x[3]);
+        } else {
+#pragma unroll
+            for (int u = 0; u < 4; u++)
+                if (t + u < k.T) op[u] = x[u];
+        }
+        if (want_flags) {
+            uint8_t* fp = k.flags + c * k.stride + t;
+#pragma unroll
+            for (int u = 0; u < 4; u++)
+                if (t + u < k.T) fp[u] = ftile[(size_t)(4 * q + u) * k.C + c];
+        }
+    }
+    if (counts && seg.n_fd > 0) {
+        // per-step counts of this lane (16-bit fields), wave sums, then global
+        for (int s = 0; s < 8; s++) {
+            const uint32_t v = (uint32_t)((cntp[s >> 2] >> (16 * (s & 3))) & 0xFFFFu);
+            const uint32_t tot = wave_add_u32(v);
+            if ((tid & 63) == 0 && tot) atomicAdd(&s_cnt[s], (unsigned long long)tot);
+        }
+        __syncthreads();
+        if (tid < 8 && s_cnt[tid]) atomicAdd(&counts[(int64_t)bm.cidx * count_stride + tid], s_cnt[tid]);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Wide fallback kernels: work lists of rows / time samples, big integers
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr int kWideNT = 256;
+constexpr int kAccW = 2 * kAccS + kAccQ;   // counters per thread: +S, -S, S2
+
+// value x after the first m TD steps of the records r
+__device__ inline float td_apply_prefix(float x, const float4* r, int m) {
+    for (int j = 0; j < m; j++) x = (x < r[j].x || x > r[j].y) ? r[j].z : x;
+    return x;
+}
+
+}  // namespace
+
+__global__ __launch_bounds__(kWideNT) void k_td_wide_f32(const DevBeam* __restrict__ all,
+                                                         const unsigned* __restrict__ wide_n,
+                                                         const int2* __restrict__ items, Segment seg,
+                                                         float4* __restrict__ rec,
+                                                         unsigned long long* __restrict__ counts,
+                                                         int count_stride) {
+    __shared__ uint64_t s_acc[kWideNT * kAccW];
+    __shared__ uint64_t s_tot[kAccW];
+    __shared__ float4 s_rec[kMaxSteps];
+    __shared__ uint32_t s_hist[(kWideNT / 64) * 256], s_tot4[kWideNT / 64], s_sel[2];
+    __shared__ unsigned long long s_cnt;
+    const int tid = threadIdx.x;
+    const unsigned nitems = *wide_n;
+    for (unsigned it = blockIdx.x; it < nitems; it += gridDim.x) {
+        const int2 item = items[it];
+        const DevBeam& bm = all[item.x];
+        const int64_t c = item.y;
+        const int64_t T = bm.T;
+        const float* row = (const float*)bm.in + c * bm.stride;
+        const uint32_t n = (uint32_t)T;
+        for (int j = 0; j < seg.n_td; j++) {
+            const SegStep& st = seg.td[j];
+            uint64_t* a = s_acc + tid * kAccW;
+            for (int l = 0; l < kAccW; l++) a[l] = 0;
+            for (int64_t i = tid; i < T; i += kWideNT)
+                acc_add_f32(a, a + kAccS, a + 2 * kAccS, __float_as_uint(td_apply_prefix(row[i], s_rec, j)));
+            __syncthreads();
+            for (int l = tid; l < kAccW; l += kWideNT) {
+                uint64_t t = 0;
+                for (int th = 0; th < kWideNT; th++) t += s_acc[th * kAccW + l];
+                s_tot[l] = t;
+            }
+            float med = 0.0f;
+            if (st.replace == RFIM_REPLACE_MEDIAN) {
+                const uint32_t key = wg_select_key<kWideNT>((uint64_t)(n - 1) / 2, s_hist, s_tot4, s_sel, [&](auto&& add) {
+                    for (int64_t i = tid; i < T; i += kWideNT)
+                        add(f32_key(__float_as_uint(td_apply_prefix(row[i], s_rec, j))));
+                });
+                med = __uint_as_float(key_f32(key));
+            }
+            __syncthreads();
+            if (tid == 0) {
+                Big P, N, S1, S2, D, t;
+                big_from_counters(P, s_tot, kAccS);
+                big_from_counters(N, s_tot + kAccS, kAccS);
+                big_from_counters(S2, s_tot + 2 * kAccS, kAccQ);
+                big_sub(S1, P, N);
+                big_mul_u64(D, S2, n);
+                big_mul(t, S1, S1);
+                big_sub(D, D, t);
+                float lo, hi;
+                big_thresholds(S1, n, 1u, D, st.kx, &lo, &hi);
+                const float r = st.replace == RFIM_REPLACE_MEDIAN ? med : big_round_ratio_f32(S1, n, kRN);
+                s_rec[j] = make_float4(lo, hi, r, 0.0f);
+                rec[(bm.rec0 + c) * seg.n_td + j] = s_rec[j];
+                s_cnt = 0;
+            }
+            __syncthreads();
+            uint32_t cnt = 0;
+            const float4 rj = s_rec[j];
+            for (int64_t i = tid; i < T; i += kWideNT) {
+                const float x = td_apply_prefix(row[i], s_rec, j);
+                cnt += (x < rj.x || x > rj.y) ? 1u : 0u;
+            }
+            cnt = wave_add_u32(cnt);
+            if ((tid & 63) == 0 && cnt) atomicAdd(&s_cnt, (unsigned long long)cnt);
+            __syncthreads();
+            if (tid == 0 && counts && s_cnt && st.bit >= 0)
+                atomicAdd(&counts[(int64_t)bm.cidx * count_stride + st.bit], s_cnt);
+            __syncthreads();
+        }
+    }
+}
+
+namespace {
+
+// exact sums of bin values p[0..B) (stride 1): +S, -S and S2 counters to Bigs
+__device__ inline void bin_sums_big(const float* p, int64_t B, Big& S, Big& Q) {
+    uint64_t a[kAccW];
+    for (int l = 0; l < kAccW; l++) a[l] = 0;
+    for (int64_t i = 0; i < B; i++) acc_add_f32(a, a + kAccS, a + 2 * kAccS, __float_as_uint(p[i]));
+    Big P, N;
+    big_from_counters(P, a, kAccS);
+    big_from_counters(N, a + kAccS, kAccS);
+    big_from_counters(Q, a + 2 * kAccS, kAccQ);
+    big_sub(S, P, N);
+}
+
+// lower median (rank (B-1)/2, totalOrder) of p[0..B): the largest key v with
+// #{x : key(x) < v} <= rank, bit by bit
+__device__ inline float bin_median_scan(const float* p, int64_t B) {
+    const int64_t rank = (B - 1) / 2;
+    uint32_t prefix = 0;
+    for (int bit = 31; bit >= 0; bit--) {
+        const uint32_t cand = prefix | (1u << bit);
+        int64_t below = 0;
+        for (int64_t i = 0; i < B; i++) below += f32_key(__float_as_uint(p[i])) < cand ? 1 : 0;
+        if (below <= rank) prefix = cand;
+    }
+    return __uint_as_float(key_f32(prefix));
+}
+
+}  // namespace
+
+__global__ __launch_bounds__(kWideNT) void k_fd_wide_f32(const DevBeam* __restrict__ all,
+                                                         const unsigned* __restrict__ wide_n,
+                                                         const int2* __restrict__ items, Segment seg,
+                                                         unsigned long long* __restrict__ counts,
+                                                         int count_stride) {
+    extern __shared__ __align__(16) uint8_t lds[];
+    __shared__ Big s_big[kWideNT / 4];
+    __shared__ unsigned long long s_cnt;
+    const int tid = threadIdx.x;
+    const unsigned nitems = *wide_n;
+    for (unsigned it = blockIdx.x; it < nitems; it += gridDim.x) {
+        const int2 item = items[it];
+        const DevBeam& bm = all[item.x];
+        const int64_t t = item.y;
+        const int64_t C = bm.C;
+        float* col = (float*)lds;
+        uint8_t* fl = lds + (size_t)C * 4;
+        const bool want_flags = seg.flags_mode != 0 && bm.flags != nullptr;
+        float* out = (float*)bm.out;
+        for (int64_t c = tid; c < C; c += kWideNT) {
+            col[c] = out[c * bm.stride + t];
+            fl[c] = 0;
+        }
+        __syncthreads();
+        for (int s = 0; s < seg.n_fd; s++) {
+            const SegStep& st = seg.fd[s];
+            const int64_t B = st.bin == 0 ? C : st.bin;
+            const int64_t nb = C / B;
+            // sum over bins of B*Q_b - S_b^2; the sum of Z_c^2 is B times that
+            Big acc, Sb, Qb, t1;
+            big_zero(acc);
+            for (int64_t bb = tid; bb < nb; bb += kWideNT) {
+                bin_sums_big(col + bb * B, B, Sb, Qb);
+                big_mul_u64(t1, Qb, (uint64_t)B);
+                big_mul(Sb, Sb, Sb);
+                big_sub(t1, t1, Sb);
+                big_add(acc, acc, t1);
+            }
+            // reduce the per-thread Bigs: four at a time per slot
+            for (int round = 0; round < 4; round++) {
+                if ((tid & 3) == round) {
+                    if (round == 0) s_big[tid >> 2] = acc;
+                    else big_add(s_big[tid >> 2], s_big[tid >> 2], acc);
+                }
+                __syncthreads();
+            }
+            if (tid == 0) {
+                for (int i = 1; i < kWideNT / 4; i++) big_add(s_big[0], s_big[0], s_big[i]);
+                s_cnt = 0;
+            }
+            __syncthreads();
+            Big R;
+            big_mul_u64(R, s_big[0], (uint64_t)B);
+            uint32_t cnt = 0;
+            for (int64_t bb = tid; bb < nb; bb += kWideNT) {
+                float* p = col + bb * B;
+                bin_sums_big(p, B, Sb, Qb);
+                float lo, hi;
+                big_thresholds(Sb, (uint32_t)B, (uint32_t)C, R, st.kx, &lo, &hi);
+                bool any = false;
+                for (int64_t i = 0; i < B; i++) any |= p[i] < lo || p[i] > hi;
+                if (!any) continue;
+                const float r = st.replace == RFIM_REPLACE_MEDIAN ? bin_median_scan(p, B)
+                                                                  : big_round_ratio_f32(Sb, (uint32_t)B, kRN);
+                for (int64_t i = 0; i < B; i++) {
+                    if (p[i] < lo || p[i] > hi) {
+                        p[i] = r;
+                        cnt++;
+                        if (st.bit >= 0) fl[bb * B + i] |= (uint8_t)(1u << st.bit);
+                    }
+                }
+            }
+            cnt = wave_add_u32(cnt);
+            if ((tid & 63) == 0 && cnt) atomicAdd(&s_cnt, (unsigned long long)cnt);
+            __syncthreads();
+            if (tid == 0 && counts && s_cnt && st.bit >= 0)
+                atomicAdd(&counts[(int64_t)bm.cidx * count_stride + st.bit], s_cnt);
+            __syncthreads();
+        }
+        for (int64_t c = tid; c < C; c += kWideNT) {
+            out[c * bm.stride + t] = col[c];
+            if (want_flags && fl[c]) bm.flags[c * bm.stride + t] |= fl[c];
+        }
+        __syncthreads();
+    }
+}
+
+// appends items (gidx, 0..n-1) to a wide list: every row (or time sample) of
+// a beam that the fast kernels do not handle
+__global__ void k_list_all(unsigned* __restrict__ wide_n, int2* __restrict__ items, int gidx, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const unsigned slot = atomicAdd(wide_n, 1u);
+        items[slot] = make_int2(gidx, (int)i);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+
+hipError_t launch_td_rows_f32(const DevBeam* d_beams, int nbeams, int64_t total_rows, int nt, int vpt,
+                              const Segment& seg, float4* rec, unsigned* wide_n, int2* wide_items,
+                              unsigned long long* counts, int count_stride, hipStream_t s) {
+    if (total_rows <= 0) return hipSuccess;
+    const dim3 grid((unsigned)total_rows);
+#define RFIM_TDF(NT_, VPT_)                                                                           \
+    if (nt == NT_ && vpt == VPT_) {                                                                   \
+        hipLaunchKernelGGL((k_td_rows_f32<NT_, VPT_>), grid, dim3(NT_), 0, s, d_beams, nbeams, seg, rec, \
+                           wide_n, wide_items, counts, count_stride);                                \
+        return hipGetLastError();                                                                     \
+    }
+    RFIM_TDF(256, 1)
+    RFIM_TDF(256, 4)
+    RFIM_TDF(256, 16)
+    RFIM_TDF(1024, 8)
+    RFIM_TDF(1024, 16)
+    RFIM_TDF(1024, 32)
+    RFIM_TDF(1024, 64)
+#undef RFIM_TDF
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_fused_f32(const DevBeam* d_beams, int nbeams, int64_t total_tiles, int B, int bpl,
+                            const Segment& seg, const float4* rec, size_t lds_bytes, unsigned* wide_n,
+                            int2* wide_items, unsigned long long* counts, int count_stride, hipStream_t s) {
+    if (total_tiles <= 0) return hipSuccess;
+    const dim3 grid((unsigned)total_tiles);
+#define RFIM_FF(B_, BPL_)                                                                              \
+    if (B == B_ && bpl == BPL_) {                                                                      \
+        hipLaunchKernelGGL((k_fused_f32<B_, BPL_>), grid, dim3(kF32Block), lds_bytes, s, d_beams, nbeams, \
+                           total_tiles, seg, rec, wide_n, wide_items, counts, count_stride);           \
+        return hipGetLastError();                                                                      \
+    }
+    RFIM_FF(0, 1)
+    RFIM_FF(8, 1)
+    RFIM_FF(8, 2)
+    RFIM_FF(16, 1)
+    RFIM_FF(16, 2)
+    RFIM_FF(32, 1)
+    RFIM_FF(32, 2)
+    RFIM_FF(64, 1)
+#undef RFIM_FF
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_td_wide_f32(const DevBeam* d_all, const unsigned* wide_n, const int2* items, int grid,
+                              const Segment& seg, float4* rec, unsigned long long* counts, int count_stride,
+                              hipStream_t s) {
+    if (grid <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_td_wide_f32, dim3(grid), dim3(kWideNT), 0, s, d_all, wide_n, items, seg, rec, counts,
+                       count_stride);
+    return hipGetLastError();
+}
+
+hipError_t launch_fd_wide_f32(const DevBeam* d_all, const unsigned* wide_n, const int2* items, int grid,
+                              int64_t max_C, const Segment& seg, unsigned long long* counts, int count_stride,
+                              hipStream_t s) {
+    if (grid <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fd_wide_f32, dim3(grid), dim3(kWideNT), (size_t)max_C * 5, s, d_all, wide_n, items, seg,
+                       counts, count_stride);
+    return hipGetLastError();
+}
+
+hipError_t launch_list_all(unsigned* wide_n, int2* items, int gidx, int64_t n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    const int blocks = (int)std::min<int64_t>((n + 255) / 256, 1024);
+    hipLaunchKernelGGL(k_list_all, dim3(blocks), dim3(256), 0, s, wide_n, items, gidx, n);
+    return hipGetLastError();
+}
+
+}  // namespace rfim

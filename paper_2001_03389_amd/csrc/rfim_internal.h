@@ -47,12 +47,13 @@ struct DevBeam {
     void* out;
     uint8_t* flags;
     int64_t C, T, stride;
-    int64_t row0;    // first global row (TD records) of this beam
-    int64_t tile0;   // first global tile of this beam
+    int64_t row0;    // first row of this beam in the launch (work-group mapping)
+    int64_t tile0;   // first tile of this beam in the launch
+    int64_t rec0;    // first row of this beam in the TD record array
     int32_t Tt;      // samples per tile of the fused kernel
-    int32_t Cp;      // LDS bytes per time sample of a tile (>= C, padded)
+    int32_t Cp;      // LDS elements per time sample of a tile (>= C, padded)
     int32_t cidx;    // index of the beam in the caller's list (flag counters)
-    int32_t pad;
+    int32_t pad;     // float32: index in the call's float32 beam table (wide lists)
 };
 
 // Host launchers (defined in the .hip files).  counts (nullable) receives, per
@@ -66,5 +67,23 @@ hipError_t launch_fused_u8(const DevBeam* d_beams, int nbeams, int64_t total_til
                            const Segment& seg, const uint32_t* d_rec, size_t lds_bytes, bool vec,
                            unsigned long long* d_counts, int count_stride, hipStream_t s);
 hipError_t launch_zero_u64(unsigned long long* p, int64_t n, hipStream_t s);
+
+// float32 launchers.  TD records are float4 (Lo, H, r, 0) per row and step;
+// wide lists hold (float32 beam index, row or time sample) pairs after a
+// counter.  nt x vpt: work-group size and values per lane of the TD kernel
+// (nt * vpt >= T).  B, bpl: fast FD bin size (0 = none) and bins per lane.
+hipError_t launch_td_rows_f32(const DevBeam* d_beams, int nbeams, int64_t total_rows, int nt, int vpt,
+                              const Segment& seg, float4* rec, unsigned* wide_n, int2* wide_items,
+                              unsigned long long* counts, int count_stride, hipStream_t s);
+hipError_t launch_fused_f32(const DevBeam* d_beams, int nbeams, int64_t total_tiles, int B, int bpl,
+                            const Segment& seg, const float4* rec, size_t lds_bytes, unsigned* wide_n,
+                            int2* wide_items, unsigned long long* counts, int count_stride, hipStream_t s);
+hipError_t launch_td_wide_f32(const DevBeam* d_all, const unsigned* wide_n, const int2* items, int grid,
+                              const Segment& seg, float4* rec, unsigned long long* counts, int count_stride,
+                              hipStream_t s);
+hipError_t launch_fd_wide_f32(const DevBeam* d_all, const unsigned* wide_n, const int2* items, int grid,
+                              int64_t max_C, const Segment& seg, unsigned long long* counts, int count_stride,
+                              hipStream_t s);
+hipError_t launch_list_all(unsigned* wide_n, int2* items, int gidx, int64_t n, hipStream_t s);
 
 }  // namespace rfim

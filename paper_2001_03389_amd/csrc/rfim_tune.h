@@ -1,0 +1,46 @@
+// Tuning parameters of a plan, the tuning cache (a JSON file of saved
+// configurations, Section III of the paper: configurations found by the
+// auto-tuner are saved and reused in production) and the host helpers the
+// auto-tuner shares with the plan code.
+#pragma once
+
+#include <string>
+
+#include "rfim_internal.h"
+
+namespace rfim {
+
+struct TuneParams {
+    int u8_tile_cap = 64;        // largest uint8 fused-kernel tile (samples, power of two)
+    size_t f32_lds = 81920;      // LDS budget of a float32 fused work-group (bytes)
+    int f32_tile_cap = 64;       // largest float32 fused-kernel tile (samples)
+};
+
+// Defaults; RFIM_TILE_T, RFIM_F32_LDS and RFIM_F32_TILE_T in the environment
+// override them (experiments).
+TuneParams default_tune();
+
+// Cache key of an ordered list of beam shapes (dtype, nchan, nsamp,
+// row_stride, flags on/off) and a step list.
+std::string tune_key(const rfim_beam* shapes, int32_t nbeams, const rfim_step* steps, int32_t nsteps);
+
+// RFIM_OK and *out filled when the cache holds the key; RFIM_ERR_UNSUPPORTED
+// when the file or the key is missing; RFIM_ERR_INVALID_ARG for a malformed
+// entry.
+rfim_status tune_cache_lookup(const char* path, const rfim_beam* shapes, int32_t nbeams,
+                              const rfim_step* steps, int32_t nsteps, TuneParams* out);
+
+// Adds or replaces the key's entry (the file is rewritten through a
+// temporary and a rename).
+rfim_status tune_cache_store(const char* path, const rfim_beam* shapes, int32_t nbeams,
+                             const rfim_step* steps, int32_t nsteps, const TuneParams& p, double ms,
+                             int candidates);
+
+// Host helpers defined in rfim_api.hip.
+KExact make_k(double k);
+size_t elem_size(int32_t dt);
+rfim_status validate(const rfim_beam* beams, int32_t nbeams, const rfim_step* steps, int32_t nsteps);
+rfim_status plan_create_tuned(const rfim_beam* shapes, int32_t nbeams, const rfim_step* steps, int32_t nsteps,
+                              const TuneParams& tune, rfim_plan** out);
+
+}  // namespace rfim

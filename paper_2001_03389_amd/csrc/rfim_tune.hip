@@ -1,0 +1,363 @@
+// Auto-tuner and tuning cache (Section III of the paper: the kernels'
+// parameters are tuned per setup and platform, and the configurations found
+// are saved for production runs).
+//
+// rfim_autotune allocates beams of the requested shapes, fills them with a
+// deterministic pseudo-random pattern on the device, and times every
+// candidate configuration with HIP events.  A candidate is admissible only if
+// its outputs and flags are bit-identical to the default configuration's
+// (the cuts are exact, so every launch shape must agree).  The fastest
+// admissible candidate is written to the JSON cache file under a key made of
+// the beam shapes and the step list; rfim_plan_create reads it back.
+//
+// Cache file: one JSON object; each entry sits on its own line,
+//   "<key>": {"u8_tile_cap": 64, "f32_lds": 81920, "f32_tile_cap": 64, "ms": 1.5, "candidates": 9}
+#include <algorithm>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <fstream>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "rfim_tune.h"
+
+namespace rfim {
+
+TuneParams default_tune() {
+    TuneParams p;
+    if (const char* e = std::getenv("RFIM_TILE_T")) {
+        const int v = std::atoi(e);
+        if (v >= 4) p.u8_tile_cap = v;
+    }
+    if (const char* e = std::getenv("RFIM_F32_LDS")) {
+        const long v = std::atol(e);
+        if (v > 0) p.f32_lds = (size_t)v;
+    }
+    if (const char* e = std::getenv("RFIM_F32_TILE_T")) {
+        const int v = std::atoi(e);
+        if (v >= 4) p.f32_tile_cap = v;
+    }
+    return p;
+}
+
+std::string tune_key(const rfim_beam* shapes, int32_t nbeams, const rfim_step* steps, int32_t nsteps) {
+    std::string k;
+    char buf[160];
+    for (int i = 0; i < nbeams; i++) {
+        const rfim_beam& b = shapes[i];
+        std::snprintf(buf, sizeof buf, "%s%s%lldx%lld/%lld%s", i ? "," : "", b.dtype == RFIM_U8 ? "u8:" : "f32:",
+                      (long long)b.nchan, (long long)b.nsamp, (long long)b.row_stride, b.flags ? "+f" : "");
+        k += buf;
+    }
+    k += ";";
+    for (int s = 0; s < nsteps; s++) {
+        const rfim_step& st = steps[s];
+        std::snprintf(buf, sizeof buf, "%s%s:%.17g:%s:%lld", s ? "," : "", st.domain == RFIM_TD ? "td" : "fd", st.k,
+                      st.replace == RFIM_REPLACE_MEDIAN ? "median" : "mean", (long long)st.bin_size);
+        k += buf;
+    }
+    return k;
+}
+
+namespace {
+
+std::vector<std::string> read_lines(const char* path, bool* exists) {
+    std::vector<std::string> lines;
+    std::ifstream f(path);
+    *exists = (bool)f;
+    std::string l;
+    while (f && std::getline(f, l)) lines.push_back(l);
+    return lines;
+}
+
+// value of "name": <number> within an entry line
+bool field(const std::string& line, const char* name, double* v) {
+    const std::string pat = std::string("\"") + name + "\":";
+    const size_t p = line.find(pat);
+    if (p == std::string::npos) return false;
+    const char* s = line.c_str() + p + pat.size();
+    char* end = nullptr;
+    *v = std::strtod(s, &end);
+    return end != s;
+}
+
+std::string entry_prefix(const std::string& key) { return "  \"" + key + "\": {"; }
+
+}  // namespace
+
+rfim_status tune_cache_lookup(const char* path, const rfim_beam* shapes, int32_t nbeams,
+                              const rfim_step* steps, int32_t nsteps, TuneParams* out) {
+    bool exists = false;
+    const std::vector<std::string> lines = read_lines(path, &exists);
+    if (!exists) return RFIM_ERR_UNSUPPORTED;
+    const std::string pre = entry_prefix(tune_key(shapes, nbeams, steps, nsteps));
+    for (const std::string& l : lines) {
+        if (l.compare(0, pre.size(), pre) != 0) continue;
+        double a = 0, b = 0, c = 0;
+        if (!field(l, "u8_tile_cap", &a) || !field(l, "f32_lds", &b) || !field(l, "f32_tile_cap", &c))
+            return RFIM_ERR_INVALID_ARG;
+        if (a < 4 || a > 64 || b < 1024 || b > (1 << 20) || c < 4 || c > 64) return RFIM_ERR_INVALID_ARG;
+        out->u8_tile_cap = (int)a;
+        out->f32_lds = (size_t)b;
+        out->f32_tile_cap = (int)c;
+        return RFIM_OK;
+    }
+    return RFIM_ERR_UNSUPPORTED;
+}
+
+rfim_status tune_cache_store(const char* path, const rfim_beam* shapes, int32_t nbeams,
+                             const rfim_step* steps, int32_t nsteps, const TuneParams& p, double ms,
+                             int candidates) {
+    bool exists = false;
+    const std::vector<std::string> lines = read_lines(path, &exists);
+    const std::string pre = entry_prefix(tune_key(shapes, nbeams, steps, nsteps));
+    std::vector<std::string> entries;
+    for (const std::string& l : lines) {
+        if (l.size() < 4 || l.compare(0, 3, "  \"") != 0) continue;   // braces and blank lines
+        if (l.compare(0, pre.size(), pre) == 0) continue;             // replaced below
+        std::string e = l;
+        if (!e.empty() && e.back() == ',') e.pop_back();
+        entries.push_back(e);
+    }
+    char buf[256];
+    std::snprintf(buf, sizeof buf,
+                  "\"u8_tile_cap\": %d, \"f32_lds\": %zu, \"f32_tile_cap\": %d, \"ms\": %.6f, \"candidates\": %d}",
+                  p.u8_tile_cap, p.f32_lds, p.f32_tile_cap, ms, candidates);
+    entries.push_back(pre + buf);
+    const std::string tmp = std::string(path) + ".tmp";
+    {
+        std::ofstream f(tmp, std::ios::trunc);
+        if (!f) return RFIM_ERR_INVALID_ARG;
+        f << "{\n";
+        for (size_t i = 0; i < entries.size(); i++) f << entries[i] << (i + 1 < entries.size() ? ",\n" : "\n");
+        f << "}\n";
+        if (!f) return RFIM_ERR_INVALID_ARG;
+    }
+    if (std::rename(tmp.c_str(), path) != 0) return RFIM_ERR_INVALID_ARG;
+    return RFIM_OK;
+}
+
+namespace {
+
+// ---- device helpers of the tuner -------------------------------------------
+
+__device__ inline uint32_t mix32(uint64_t x) {
+    x ^= x >> 33;
+    x *= 0xff51afd7ed558ccdull;
+    x ^= x >> 33;
+    x *= 0xc4ceb9fe1a85ec53ull;
+    x ^= x >> 33;
+    return (uint32_t)x;
+}
+
+// deterministic test pattern: uint8 around a per-row level with rare spikes,
+// float32 a sum of uniforms (roughly normal) with rare large values
+__global__ void k_fill(void* p, int dtype, int64_t rows, int64_t stride, int64_t T, uint64_t seed) {
+    const int64_t n = rows * stride;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t r = i / stride, t = i - r * stride;
+        const uint32_t h = mix32(seed * 0x9E3779B97F4A7C15ull + (uint64_t)i);
+        const uint32_t hr = mix32(seed ^ (0xABCDull + (uint64_t)r * 77));
+        const bool spike = (h & 1023u) == 0;
+        if (dtype == RFIM_U8) {
+            int v = 60 + (int)(hr % 40) + (int)((h >> 10) & 15) + (int)((h >> 14) & 15) - 15;
+            if (spike) v += 100;
+            ((uint8_t*)p)[i] = (uint8_t)(t < T ? (v < 0 ? 0 : (v > 255 ? 255 : v)) : 0);
+        } else {
+            float v = ((float)((h >> 8) & 255u) + (float)((h >> 16) & 255u) + (float)(h >> 24) - 382.5f) / 128.0f;
+            if (spike) v += 12.0f;
+            ((float*)p)[i] = t < T ? v : 0.0f;
+        }
+    }
+}
+
+// number of differing bytes between a and b
+__global__ void k_count_diff(const uint8_t* a, const uint8_t* b, int64_t n, unsigned long long* out) {
+    unsigned long long c = 0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        c += a[i] != b[i];
+    if (c) atomicAdd(out, c);
+}
+
+struct TBeam {
+    void* in = nullptr;
+    void* out = nullptr;
+    void* ref = nullptr;
+    uint8_t* fl = nullptr;
+    uint8_t* fref = nullptr;
+    size_t bytes = 0, fbytes = 0;
+};
+
+void free_beams(std::vector<TBeam>& tb) {
+    for (auto& t : tb) {
+        if (t.in) (void)hipFree(t.in);
+        if (t.out) (void)hipFree(t.out);
+        if (t.ref) (void)hipFree(t.ref);
+        if (t.fl) (void)hipFree(t.fl);
+        if (t.fref) (void)hipFree(t.fref);
+    }
+    tb.clear();
+}
+
+}  // namespace
+}  // namespace rfim
+
+using namespace rfim;
+
+extern "C" {
+
+rfim_status rfim_tune_lookup(const char* path, const rfim_beam* shapes, int32_t nbeams, const rfim_step* steps,
+                             int32_t nsteps, int64_t* out3) {
+    if (!path || !shapes || nbeams < 1 || !steps || nsteps < 1 || !out3) return RFIM_ERR_INVALID_ARG;
+    TuneParams p;
+    const rfim_status st = tune_cache_lookup(path, shapes, nbeams, steps, nsteps, &p);
+    if (st != RFIM_OK) return st;
+    out3[0] = p.u8_tile_cap;
+    out3[1] = (int64_t)p.f32_lds;
+    out3[2] = p.f32_tile_cap;
+    return RFIM_OK;
+}
+
+rfim_status rfim_tune_store(const char* path, const rfim_beam* shapes, int32_t nbeams, const rfim_step* steps,
+                            int32_t nsteps, const int64_t* params3, double ms) {
+    if (!path || !shapes || nbeams < 1 || !steps || nsteps < 1 || !params3) return RFIM_ERR_INVALID_ARG;
+    TuneParams p;
+    p.u8_tile_cap = (int)params3[0];
+    p.f32_lds = (size_t)params3[1];
+    p.f32_tile_cap = (int)params3[2];
+    if (p.u8_tile_cap < 4 || p.u8_tile_cap > 64 || p.f32_lds < 1024 || p.f32_lds > (1u << 20) ||
+        p.f32_tile_cap < 4 || p.f32_tile_cap > 64)
+        return RFIM_ERR_INVALID_ARG;
+    return tune_cache_store(path, shapes, nbeams, steps, nsteps, p, ms, 0);
+}
+
+rfim_status rfim_autotune(const rfim_beam* shapes, int32_t nbeams, const rfim_step* steps, int32_t nsteps,
+                          const char* tune_cache_path, void* stream, double* best_ms) {
+    if (!shapes || nbeams < 1 || !steps || nsteps < 1 || !tune_cache_path) return RFIM_ERR_INVALID_ARG;
+    std::vector<rfim_beam> sh(shapes, shapes + nbeams);
+    for (auto& b : sh) b.in = b.out = (void*)(uintptr_t)4096;
+    rfim_status st = validate(sh.data(), nbeams, steps, nsteps);
+    if (st != RFIM_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    bool any_u8 = false, any_f32 = false;
+    for (auto& b : sh) (b.dtype == RFIM_U8 ? any_u8 : any_f32) = true;
+
+    // beams with the test pattern, outputs and reference outputs
+    std::vector<TBeam> tb(nbeams);
+    for (int i = 0; i < nbeams && st == RFIM_OK; i++) {
+        const rfim_beam& b = shapes[i];
+        TBeam& t = tb[i];
+        t.bytes = (size_t)b.nchan * (size_t)b.row_stride * elem_size(b.dtype);
+        t.fbytes = b.flags ? (size_t)b.nchan * (size_t)b.row_stride : 0;
+        if (hipMalloc(&t.in, t.bytes) != hipSuccess || hipMalloc(&t.out, t.bytes) != hipSuccess ||
+            hipMalloc(&t.ref, t.bytes) != hipSuccess)
+            st = RFIM_ERR_OUT_OF_MEMORY;
+        if (st == RFIM_OK && t.fbytes &&
+            (hipMalloc((void**)&t.fl, t.fbytes) != hipSuccess || hipMalloc((void**)&t.fref, t.fbytes) != hipSuccess))
+            st = RFIM_ERR_OUT_OF_MEMORY;
+        if (st == RFIM_OK) {
+            hipLaunchKernelGGL(k_fill, dim3(1024), dim3(256), 0, s, t.in, b.dtype, b.nchan, b.row_stride, b.nsamp,
+                               (uint64_t)(i + 1));
+            if (hipGetLastError() != hipSuccess) st = RFIM_ERR_DEVICE;
+        }
+    }
+    unsigned long long* d_diff = nullptr;
+    if (st == RFIM_OK && hipMalloc(&d_diff, sizeof(unsigned long long)) != hipSuccess) st = RFIM_ERR_OUT_OF_MEMORY;
+    if (st != RFIM_OK) {
+        free_beams(tb);
+        if (d_diff) (void)hipFree(d_diff);
+        return st;
+    }
+    auto beams_to = [&](bool ref) {
+        std::vector<rfim_beam> v(sh);
+        for (int i = 0; i < nbeams; i++) {
+            v[i].in = tb[i].in;
+            v[i].out = ref ? tb[i].ref : tb[i].out;
+            v[i].flags = shapes[i].flags ? (ref ? tb[i].fref : tb[i].fl) : nullptr;
+        }
+        return v;
+    };
+
+    // candidates: the default first (it produces the reference outputs)
+    std::vector<TuneParams> cands;
+    const TuneParams def = default_tune();
+    cands.push_back(def);
+    const int u8caps[] = {16, 32, 64};
+    const size_t f32lds[] = {40960, 81920, 163840};
+    const int f32caps[] = {8, 64};
+    for (int a : u8caps)
+        for (size_t l : f32lds)
+            for (int c : f32caps) {
+                if (!any_u8 && a != def.u8_tile_cap) continue;
+                if (!any_f32 && (l != def.f32_lds || c != def.f32_tile_cap)) continue;
+                TuneParams p;
+                p.u8_tile_cap = a;
+                p.f32_lds = l;
+                p.f32_tile_cap = c;
+                if (p.u8_tile_cap == def.u8_tile_cap && p.f32_lds == def.f32_lds && p.f32_tile_cap == def.f32_tile_cap)
+                    continue;
+                cands.push_back(p);
+            }
+
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    (void)hipEventCreate(&e0);
+    (void)hipEventCreate(&e1);
+    double best = 1e30;
+    TuneParams bestp = def;
+    int tried = 0;
+    const int reps = 5;
+    for (size_t ci = 0; ci < cands.size() && st == RFIM_OK; ci++) {
+        rfim_plan* plan = nullptr;
+        if (plan_create_tuned(shapes, nbeams, steps, nsteps, cands[ci], &plan) != RFIM_OK) continue;
+        const std::vector<rfim_beam> bv = beams_to(ci == 0);
+        rfim_status rs = rfim_pipeline_run(bv.data(), nbeams, steps, nsteps, plan, stream);   // warm-up
+        bool ok = rs == RFIM_OK;
+        if (ok && ci > 0) {
+            // bit-identical to the default configuration, or rejected
+            if (hipMemsetAsync(d_diff, 0, sizeof(unsigned long long), s) != hipSuccess) ok = false;
+            for (int i = 0; i < nbeams && ok; i++) {
+                hipLaunchKernelGGL(k_count_diff, dim3(1024), dim3(256), 0, s, (const uint8_t*)tb[i].out,
+                                   (const uint8_t*)tb[i].ref, (int64_t)tb[i].bytes, d_diff);
+                if (tb[i].fbytes)
+                    hipLaunchKernelGGL(k_count_diff, dim3(1024), dim3(256), 0, s, (const uint8_t*)tb[i].fl,
+                                       (const uint8_t*)tb[i].fref, (int64_t)tb[i].fbytes, d_diff);
+            }
+            unsigned long long diff = 1;
+            if (ok && hipMemcpyAsync(&diff, d_diff, sizeof diff, hipMemcpyDeviceToHost, s) == hipSuccess &&
+                hipStreamSynchronize(s) == hipSuccess)
+                ok = diff == 0;
+            else
+                ok = false;
+            if (!ok) std::fprintf(stderr, "rfim_autotune: candidate %zu differs from the default, rejected\n", ci);
+        }
+        if (ok) {
+            (void)hipEventRecord(e0, s);
+            for (int r = 0; r < reps && ok; r++)
+                ok = rfim_pipeline_run(bv.data(), nbeams, steps, nsteps, plan, stream) == RFIM_OK;
+            (void)hipEventRecord(e1, s);
+            float ms = 0.f;
+            if (ok && hipEventSynchronize(e1) == hipSuccess && hipEventElapsedTime(&ms, e0, e1) == hipSuccess) {
+                tried++;
+                const double per = ms / reps;
+                if (per < best) {
+                    best = per;
+                    bestp = cands[ci];
+                }
+            }
+        }
+        (void)rfim_plan_destroy(plan);
+        if (ci == 0 && !ok) st = RFIM_ERR_DEVICE;   // the default must run
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipStreamSynchronize(s);
+    free_beams(tb);
+    (void)hipFree(d_diff);
+    if (st != RFIM_OK) return st;
+    if (best_ms) *best_ms = best;
+    return tune_cache_store(tune_cache_path, shapes, nbeams, steps, nsteps, bestp, best, tried);
+}
+
+}  // extern "C"

@@ -1,0 +1,101 @@
+"""GPU: the HIP-graph form of a plan and the auto-tuner.  A captured graph
+is replayed several times with eager work and synchronisation in between;
+every replay must give the eager run's bytes and flag counts.  The auto-tuner
+writes a cache entry whose plan gives the default plan's bytes."""
+from __future__ import annotations
+
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def rf():
+    import torch
+    assert torch.cuda.is_available(), "needs a GPU"
+    import paper_2001_03389_amd as m
+    m.lib()
+    return m
+
+
+def mixed_beams():
+    rng = np.random.default_rng(44)
+    return [rng.normal(80, 10, (256, 3000)).clip(0, 255).astype(np.uint8),
+            rng.standard_normal((128, 2500)).astype(np.float32),
+            rng.normal(70, 9, (64, 1777)).clip(0, 255).astype(np.uint8),
+            (rng.standard_normal((96, 5000)) * 2).astype(np.float32)]
+
+
+STEPS = [synth.td(3.5), synth.td(3.0, "median"), synth.fd(2.75, 32), synth.fd(2.5, 32, "median")]
+
+
+def test_graph_replays_match_eager(rf):
+    import torch
+    dev = torch.device("cuda:0")
+    host = mixed_beams()
+    ins = [torch.from_numpy(h).to(dev) for h in host]
+    outs_e = [torch.empty_like(x) for x in ins]
+    fl_e = [torch.zeros(x.shape, dtype=torch.uint8, device=dev) for x in ins]
+    pe = rf.Plan(ins, STEPS, outputs=outs_e, flags=fl_e)
+    rf.rfim_pipeline_run(ins, STEPS, outputs=outs_e, flags=fl_e, plan=pe)
+    torch.cuda.synchronize()
+    want_counts = pe.flag_counts()
+    want = [o.cpu().numpy().view(np.uint8).copy() for o in outs_e]
+    want_f = [f.cpu().numpy().copy() for f in fl_e]
+    pe.close()
+
+    outs = [torch.empty_like(x) for x in ins]
+    fls = [torch.zeros(x.shape, dtype=torch.uint8, device=dev) for x in ins]
+    pg = rf.Plan(ins, STEPS, outputs=outs, flags=fls)
+    stream = torch.cuda.Stream()
+    pg.capture(ins, outputs=outs, flags=fls, stream=stream)
+    for rep in range(4):
+        say(f"replay {rep}")
+        for o in outs:
+            o.fill_(0)          # eager work between replays
+        for f in fls:
+            f.fill_(0x5A)
+        torch.cuda.synchronize()
+        pg.replay(stream=stream)
+        stream.synchronize()
+        got = [o.cpu().numpy().view(np.uint8) for o in outs]
+        for i in range(len(host)):
+            np.testing.assert_array_equal(got[i], want[i], err_msg=f"replay {rep} beam {i}")
+            np.testing.assert_array_equal(fls[i].cpu().numpy(), want_f[i], err_msg=f"replay {rep} beam {i} flags")
+        assert pg.flag_counts() == want_counts
+    pg.close()
+
+
+def test_autotune_cache_gives_identical_plan(rf, tmp_path):
+    import torch
+    dev = torch.device("cuda:0")
+    host = mixed_beams()
+    ins = [torch.from_numpy(h).to(dev) for h in host]
+    shapes = [rf.shape_beam("u8" if h.dtype == np.uint8 else "f32", *h.shape) for h in host]
+    cache = str(tmp_path / "tune.json")
+    say("autotune")
+    ms = rf.autotune(shapes, STEPS, cache)
+    assert ms > 0
+    params = rf.tune_lookup(cache, shapes, STEPS)
+    assert params is not None
+    say(f"tuned {params} {ms:.3f} ms")
+    res = []
+    for tc in (None, cache):
+        outs = [torch.empty_like(x) for x in ins]
+        p = rf.Plan(ins, STEPS, outputs=outs, tune_cache=tc)
+        rf.rfim_pipeline_run(ins, STEPS, outputs=outs, plan=p)
+        torch.cuda.synchronize()
+        res.append([o.cpu().numpy().view(np.uint8) for o in outs])
+        p.close()
+    for a, b in zip(*res):
+        np.testing.assert_array_equal(a, b)
