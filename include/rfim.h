@@ -128,6 +128,11 @@ rfim_status rfim_plan_destroy(rfim_plan* plan);
  * capture).  Replays of one plan must not overlap. */
 rfim_status rfim_plan_capture(rfim_plan* plan, const rfim_beam* beams, int32_t nbeams, void* stream);
 rfim_status rfim_plan_replay(rfim_plan* plan, void* stream);
+/* Replays the captured graph on other buffers of the plan's shapes: the
+ * graph's beam tables are rewritten (one host-to-device copy on `stream`
+ * ahead of the launch) with these beams' pointers.  Serving loops use it to
+ * run each batch of arrivals through one graph launch. */
+rfim_status rfim_plan_replay_on(rfim_plan* plan, const rfim_beam* beams, int32_t nbeams, void* stream);
 
 /* Auto-tuner (Section III: parameters tuned per setup and platform, the
  * configurations saved for production).  Times every candidate kernel
@@ -175,6 +180,64 @@ typedef enum {
 rfim_status rfim_plan_set_timing(rfim_plan* plan, int32_t enable);
 rfim_status rfim_plan_kernel_times(rfim_plan* plan, int32_t kind, uint64_t* launches,
                                    double* total_ms);
+
+/* ---- Streaming serve loop ------------------------------------------------
+ * Beams deliver batches of one shape (Section IV: mitigation runs per AMBER
+ * batch; at the real-time rate one batch per batch period per beam).  The
+ * loop is driven by the caller on one clock (seconds; rfim_serve_now gives
+ * the loop's own steady clock, which GPU completions are measured on):
+ *   rfim_serve_submit   admits one arrival: its data (host or device memory,
+ *                       one [nchan][nsamp] batch) is copied into a slot of the
+ *                       loop's device pool; refused with RFIM_ERR_BUDGET when
+ *                       the pool (hbm_budget bytes) is full or the beam already
+ *                       has ring_depth arrivals in flight;
+ *   rfim_serve_poll     harvests finished launches (latency = completion -
+ *                       arrival) and launches batches of ready arrivals: a
+ *                       batch goes when it holds max_batch arrivals or its
+ *                       oldest arrival has waited max_wait_s;
+ *   rfim_serve_drain    launches what is pending and waits for everything;
+ *   rfim_serve_get_stats counts, latency percentiles (nearest rank) and
+ *                       misses of deadline_s.
+ * mode: RFIM_SERVE_PER_CALL (one pipeline run per arrival, then a stream
+ * synchronise), RFIM_SERVE_BATCHED (plans of up to max_batch beams),
+ * RFIM_SERVE_GRAPH (as BATCHED through one HIP graph per batch size).
+ * mock = 1 runs no GPU work: a launch of k arrivals then takes
+ * mock_launch_s + k * mock_beam_s on one in-order device (scheduler tests).
+ * Mitigation is in place in the pool slot; the loop is single-threaded (one
+ * caller thread per loop). */
+typedef enum { RFIM_SERVE_PER_CALL = 0, RFIM_SERVE_BATCHED = 1, RFIM_SERVE_GRAPH = 2 } rfim_serve_mode;
+
+typedef struct {
+    int32_t dtype;      /* rfim_dtype of every arrival */
+    int32_t reserved;   /* must be 0 */
+    int64_t nchan, nsamp;
+    int32_t ring_depth; /* arrivals in flight per beam, >= 1 */
+    int32_t max_batch;  /* arrivals per launch, 1..4096 */
+    int64_t hbm_budget; /* bytes of the device slot pool */
+    double max_wait_s;  /* >= 0 */
+    double deadline_s;  /* > 0 */
+    int32_t mode;       /* rfim_serve_mode */
+    int32_t mock;       /* 0 or 1 */
+    double mock_launch_s, mock_beam_s;
+} rfim_serve_config;
+
+typedef struct {
+    uint64_t submitted, admitted, rejected_budget, rejected_ring, completed, launches;
+    uint64_t deadline_misses, max_backlog, slots, in_flight;
+    double p50_s, p99_s, max_s, mean_batch;
+} rfim_serve_stats;
+
+typedef struct rfim_serve rfim_serve; /* opaque */
+
+rfim_status rfim_serve_create(const rfim_serve_config* cfg, const rfim_step* steps, int32_t nsteps,
+                              rfim_serve** out);
+double rfim_serve_now(const rfim_serve* srv);
+rfim_status rfim_serve_submit(rfim_serve* srv, int32_t beam, const void* src, int32_t src_on_host,
+                              double arrival_s);
+rfim_status rfim_serve_poll(rfim_serve* srv, double now_s, uint64_t* completed_total);
+rfim_status rfim_serve_drain(rfim_serve* srv, double now_s);
+rfim_status rfim_serve_get_stats(rfim_serve* srv, rfim_serve_stats* out);
+rfim_status rfim_serve_destroy(rfim_serve* srv);
 
 /* Human-readable text for a status code (static storage). */
 const char* rfim_status_string(rfim_status s);

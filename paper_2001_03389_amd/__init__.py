@@ -46,6 +46,25 @@ class rfim_step(ctypes.Structure):
                 ("k", ctypes.c_double), ("bin_size", ctypes.c_int64)]
 
 
+RFIM_SERVE_PER_CALL, RFIM_SERVE_BATCHED, RFIM_SERVE_GRAPH = 0, 1, 2
+
+
+class rfim_serve_config(ctypes.Structure):
+    _fields_ = [("dtype", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("nchan", ctypes.c_int64), ("nsamp", ctypes.c_int64),
+                ("ring_depth", ctypes.c_int32), ("max_batch", ctypes.c_int32),
+                ("hbm_budget", ctypes.c_int64), ("max_wait_s", ctypes.c_double),
+                ("deadline_s", ctypes.c_double), ("mode", ctypes.c_int32), ("mock", ctypes.c_int32),
+                ("mock_launch_s", ctypes.c_double), ("mock_beam_s", ctypes.c_double)]
+
+
+class rfim_serve_stats(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_uint64) for n in ("submitted", "admitted", "rejected_budget", "rejected_ring",
+                                                "completed", "launches", "deadline_misses", "max_backlog",
+                                                "slots", "in_flight")] + \
+               [(n, ctypes.c_double) for n in ("p50_s", "p99_s", "max_s", "mean_batch")]
+
+
 _lib = None
 
 
@@ -73,6 +92,18 @@ def lib() -> ctypes.CDLL:
         L.rfim_autotune.argtypes = [PB, i32, PS, i32, ctypes.c_char_p, vp, ctypes.POINTER(dbl)]
         L.rfim_tune_lookup.argtypes = [ctypes.c_char_p, PB, i32, PS, i32, ctypes.POINTER(i64)]
         L.rfim_tune_store.argtypes = [ctypes.c_char_p, PB, i32, PS, i32, ctypes.POINTER(i64), dbl]
+        L.rfim_plan_replay_on.argtypes = [vp, PB, i32, vp]
+        L.rfim_serve_create.argtypes = [ctypes.POINTER(rfim_serve_config), PS, i32, ctypes.POINTER(vp)]
+        L.rfim_serve_now.argtypes = [vp]
+        L.rfim_serve_now.restype = dbl
+        L.rfim_serve_submit.argtypes = [vp, i32, vp, i32, dbl]
+        L.rfim_serve_poll.argtypes = [vp, dbl, ctypes.POINTER(ctypes.c_uint64)]
+        L.rfim_serve_drain.argtypes = [vp, dbl]
+        L.rfim_serve_get_stats.argtypes = [vp, ctypes.POINTER(rfim_serve_stats)]
+        L.rfim_serve_destroy.argtypes = [vp]
+        for f in ("rfim_plan_replay_on", "rfim_serve_create", "rfim_serve_submit", "rfim_serve_poll",
+                  "rfim_serve_drain", "rfim_serve_get_stats", "rfim_serve_destroy"):
+            getattr(L, f).restype = st
         for f in ("rfim_td_sigma_cut", "rfim_fd_sigma_cut", "rfim_pipeline_run", "rfim_plan_create",
                   "rfim_plan_destroy", "rfim_plan_flag_counts", "rfim_plan_set_timing",
                   "rfim_plan_kernel_times", "rfim_plan_capture", "rfim_plan_replay", "rfim_autotune",
@@ -276,6 +307,11 @@ class Plan:
         """Launches the captured graph (rfim_plan_replay)."""
         _check(lib().rfim_plan_replay(self.handle, _stream_handle(stream)), "rfim_plan_replay")
 
+    def replay_on(self, inputs: Sequence, outputs=None, flags=None, nsamp=None, stream=None) -> None:
+        """Replays the captured graph on other buffers of the same shapes (rfim_plan_replay_on)."""
+        arr, n = _beams(inputs, outputs, flags, nsamp)
+        _check(lib().rfim_plan_replay_on(self.handle, arr, n, _stream_handle(stream)), "rfim_plan_replay_on")
+
     def flag_counts(self):
         buf = (ctypes.c_uint64 * (self.nbeams * self.nsteps))()
         _check(lib().rfim_plan_flag_counts(self.handle, buf), "rfim_plan_flag_counts")
@@ -295,6 +331,69 @@ class Plan:
     def close(self):
         if self.handle:
             lib().rfim_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Serve:
+    """Streaming serve loop (rfim_serve_*): submit arrivals, poll, drain, stats.
+    ``mock=True`` runs the scheduler with a modelled executor and no GPU work."""
+
+    def __init__(self, steps: Sequence, *, dtype="u8", nchan=1536, nsamp=12500, ring_depth=2, max_batch=8,
+                 hbm_budget=1 << 30, max_wait_s=0.002, deadline_s=1.024, mode="batched", mock=False,
+                 mock_launch_s=0.0, mock_beam_s=0.0):
+        c = rfim_serve_config()
+        c.dtype = {"u8": RFIM_U8, "f32": RFIM_F32}.get(dtype, dtype)
+        c.reserved = 0
+        c.nchan, c.nsamp = int(nchan), int(nsamp)
+        c.ring_depth, c.max_batch, c.hbm_budget = int(ring_depth), int(max_batch), int(hbm_budget)
+        c.max_wait_s, c.deadline_s = float(max_wait_s), float(deadline_s)
+        c.mode = {"per_call": RFIM_SERVE_PER_CALL, "batched": RFIM_SERVE_BATCHED,
+                  "graph": RFIM_SERVE_GRAPH}.get(mode, mode)
+        c.mock = 1 if mock else 0
+        c.mock_launch_s, c.mock_beam_s = float(mock_launch_s), float(mock_beam_s)
+        self.cfg = c
+        h = ctypes.c_void_p()
+        _check(lib().rfim_serve_create(ctypes.byref(c), make_steps(steps), len(steps), ctypes.byref(h)),
+               "rfim_serve_create")
+        self.handle = h
+
+    def now(self) -> float:
+        return float(lib().rfim_serve_now(self.handle))
+
+    def submit(self, beam: int, src=None, arrival_s: float = 0.0) -> bool:
+        """True if admitted, False if refused (budget or the beam's ring full).
+        ``src``: a torch tensor (device or host) holding one batch, or None (mock)."""
+        ptr, on_host = None, 0
+        if src is not None:
+            ptr, on_host = src.data_ptr(), 0 if src.is_cuda else 1
+        rc = lib().rfim_serve_submit(self.handle, int(beam), ptr, on_host, float(arrival_s))
+        if rc == RFIM_ERR_BUDGET:
+            return False
+        _check(rc, "rfim_serve_submit")
+        return True
+
+    def poll(self, now_s: float) -> int:
+        n = ctypes.c_uint64()
+        _check(lib().rfim_serve_poll(self.handle, float(now_s), ctypes.byref(n)), "rfim_serve_poll")
+        return int(n.value)
+
+    def drain(self, now_s: float) -> None:
+        _check(lib().rfim_serve_drain(self.handle, float(now_s)), "rfim_serve_drain")
+
+    def stats(self) -> dict:
+        st = rfim_serve_stats()
+        _check(lib().rfim_serve_get_stats(self.handle, ctypes.byref(st)), "rfim_serve_get_stats")
+        return {n: getattr(st, n) for n, _ in rfim_serve_stats._fields_}
+
+    def close(self):
+        if self.handle:
+            lib().rfim_serve_destroy(self.handle)
             self.handle = None
 
     def __del__(self):

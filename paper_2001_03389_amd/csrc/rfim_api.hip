@@ -1020,6 +1020,39 @@ rfim_status rfim_plan_replay(rfim_plan* plan, void* stream) {
     return RFIM_OK;
 }
 
+rfim_status rfim_plan_replay_on(rfim_plan* plan, const rfim_beam* beams, int32_t nbeams, void* stream) {
+    if (!plan) return RFIM_ERR_INVALID_ARG;
+    std::vector<rfim_step> steps = plan->steps;
+    rfim_status st = validate(beams, nbeams, steps.data(), (int32_t)steps.size());
+    if (st != RFIM_OK) return st;
+    st = check_plan_match(plan, beams, nbeams, steps.data(), (int32_t)steps.size());
+    if (st != RFIM_OK) return st;
+    std::lock_guard<std::mutex> lk(plan->ws.mu);
+    if (!plan->exec) return RFIM_ERR_INVALID_ARG;
+    Workspace& ws = plan->ws;
+    hipStream_t s = (hipStream_t)stream;
+    if (ws.has_last && ws.last_stream != s && hipStreamWaitEvent(s, ws.last_done, 0) != hipSuccess)
+        return RFIM_ERR_DEVICE;
+    // same shapes, so the same program layout: only the tables' pointers change
+    Program pg;
+    build_program(beams, nbeams, plan->lp, true, pg);
+    Slot* sl = nullptr;
+    const size_t bytes = sizeof(DevBeam) * std::max<size_t>(1, pg.blob.size());
+    st = ws.slot(bytes, &sl);
+    if (st != RFIM_OK) return st;
+    std::memcpy(sl->h, pg.blob.data(), sizeof(DevBeam) * pg.blob.size());
+    if (hipMemcpyAsync(plan->d_blob, sl->h, sizeof(DevBeam) * pg.blob.size(), hipMemcpyHostToDevice, s) !=
+        hipSuccess)
+        return RFIM_ERR_DEVICE;
+    if (hipGraphLaunch(plan->exec, s) != hipSuccess) return RFIM_ERR_DEVICE;
+    if (hipEventRecord(sl->ev, s) != hipSuccess) return RFIM_ERR_DEVICE;
+    sl->used = true;
+    if (hipEventRecord(ws.last_done, s) != hipSuccess) return RFIM_ERR_DEVICE;
+    ws.last_stream = s;
+    ws.has_last = true;
+    return RFIM_OK;
+}
+
 rfim_status rfim_plan_flag_counts(const rfim_plan* plan, uint64_t* host_out) {
     if (!plan || !host_out) return RFIM_ERR_INVALID_ARG;
     rfim_plan* p = const_cast<rfim_plan*>(plan);
