@@ -190,7 +190,10 @@ rfim_status rfim_plan_kernel_times(rfim_plan* plan, int32_t kind, uint64_t* laun
  *                       one [nchan][nsamp] batch) is copied into a slot of the
  *                       loop's device pool; refused with RFIM_ERR_BUDGET when
  *                       the pool (hbm_budget bytes) is full or the beam already
- *                       has ring_depth arrivals in flight;
+ *                       has ring_depth arrivals in flight.  The mitigated batch
+ *                       goes to dst (device, [nchan][nsamp], not overlapping
+ *                       the pool; must stay valid until the arrival completes)
+ *                       or, with dst NULL, stays in the slot;
  *   rfim_serve_poll     harvests finished launches (latency = completion -
  *                       arrival) and launches batches of ready arrivals: a
  *                       batch goes when it holds max_batch arrivals or its
@@ -233,7 +236,7 @@ rfim_status rfim_serve_create(const rfim_serve_config* cfg, const rfim_step* ste
                               rfim_serve** out);
 double rfim_serve_now(const rfim_serve* srv);
 rfim_status rfim_serve_submit(rfim_serve* srv, int32_t beam, const void* src, int32_t src_on_host,
-                              double arrival_s);
+                              void* dst, double arrival_s);
 rfim_status rfim_serve_poll(rfim_serve* srv, double now_s, uint64_t* completed_total);
 rfim_status rfim_serve_drain(rfim_serve* srv, double now_s);
 rfim_status rfim_serve_get_stats(rfim_serve* srv, rfim_serve_stats* out);

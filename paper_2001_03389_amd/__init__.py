@@ -96,7 +96,7 @@ def lib() -> ctypes.CDLL:
         L.rfim_serve_create.argtypes = [ctypes.POINTER(rfim_serve_config), PS, i32, ctypes.POINTER(vp)]
         L.rfim_serve_now.argtypes = [vp]
         L.rfim_serve_now.restype = dbl
-        L.rfim_serve_submit.argtypes = [vp, i32, vp, i32, dbl]
+        L.rfim_serve_submit.argtypes = [vp, i32, vp, i32, vp, dbl]
         L.rfim_serve_poll.argtypes = [vp, dbl, ctypes.POINTER(ctypes.c_uint64)]
         L.rfim_serve_drain.argtypes = [vp, dbl]
         L.rfim_serve_get_stats.argtypes = [vp, ctypes.POINTER(rfim_serve_stats)]
@@ -366,13 +366,15 @@ class Serve:
     def now(self) -> float:
         return float(lib().rfim_serve_now(self.handle))
 
-    def submit(self, beam: int, src=None, arrival_s: float = 0.0) -> bool:
+    def submit(self, beam: int, src=None, arrival_s: float = 0.0, dst=None) -> bool:
         """True if admitted, False if refused (budget or the beam's ring full).
-        ``src``: a torch tensor (device or host) holding one batch, or None (mock)."""
+        ``src``: a torch tensor (device or host) holding one batch, or None (mock);
+        ``dst``: device tensor for the mitigated batch (None: in place in the pool)."""
         ptr, on_host = None, 0
         if src is not None:
             ptr, on_host = src.data_ptr(), 0 if src.is_cuda else 1
-        rc = lib().rfim_serve_submit(self.handle, int(beam), ptr, on_host, float(arrival_s))
+        rc = lib().rfim_serve_submit(self.handle, int(beam), ptr, on_host,
+                                     dst.data_ptr() if dst is not None else None, float(arrival_s))
         if rc == RFIM_ERR_BUDGET:
             return False
         _check(rc, "rfim_serve_submit")

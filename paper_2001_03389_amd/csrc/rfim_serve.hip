@@ -36,6 +36,7 @@ struct Arrival {
     int32_t beam;
     int32_t slot;
     double t_arr;
+    void* dst;   // device output (nullptr: in place in the slot)
 };
 
 struct Running {
@@ -143,7 +144,9 @@ rfim_status launch_batch(rfim_serve* s, std::vector<Arrival>&& batch, double now
             b.nchan = s->cfg.nchan;
             b.nsamp = s->cfg.nsamp;
             b.row_stride = s->cfg.nsamp;
-            b.in = b.out = s->pool + (size_t)batch[i].slot * s->bytes;
+            void* slotp = s->pool + (size_t)batch[i].slot * s->bytes;
+            b.in = slotp;
+            b.out = batch[i].dst ? batch[i].dst : slotp;
             b.flags = nullptr;
         }
         rfim_plan*& plan = s->plans[k];
@@ -259,7 +262,8 @@ rfim_status rfim_serve_create(const rfim_serve_config* cfg, const rfim_step* ste
 
 double rfim_serve_now(const rfim_serve* s) { return s ? s->clock_now() : 0.0; }
 
-rfim_status rfim_serve_submit(rfim_serve* s, int32_t beam, const void* src, int32_t src_on_host, double arrival_s) {
+rfim_status rfim_serve_submit(rfim_serve* s, int32_t beam, const void* src, int32_t src_on_host, void* dst,
+                              double arrival_s) {
     if (!s || beam < 0 || (!s->cfg.mock && !src)) return RFIM_ERR_INVALID_ARG;
     s->st.submitted++;
     auto it = s->in_flight.find(beam);
@@ -279,7 +283,7 @@ rfim_status rfim_serve_submit(rfim_serve* s, int32_t beam, const void* src, int3
     }
     s->free_slots.pop_back();
     s->in_flight[beam]++;
-    s->pending.push_back({beam, slot, arrival_s});
+    s->pending.push_back({beam, slot, arrival_s, dst});
     s->st.admitted++;
     s->st.max_backlog = std::max<uint64_t>(s->st.max_backlog, s->pending.size());
     return RFIM_OK;

@@ -34,7 +34,7 @@ def gpu_run(rf, beams, steps, *, flags=True, inplace=False, nsamp=None, plan=Fal
     import torch
     dev = torch.device("cuda:0")
     ins = [torch.from_numpy(np.ascontiguousarray(b)).to(dev) for b in beams]
-    outs = ins if inplace else [torch.full_like(x, 1234.5) for x in ins]
+    outs = ins if inplace else [torch.full_like(x, 1234.5 if x.dtype == torch.float32 else 90) for x in ins]
     fls = [torch.full(x.shape, 0xA5, dtype=torch.uint8, device=dev) for x in ins] if flags else None
     if plan:
         p = rf.Plan(ins, steps, outputs=outs, flags=fls, nsamp=nsamp)
