@@ -168,7 +168,9 @@ typedef enum {
     RFIM_KERNEL_FUSED_F32 = 3,   /* float32 TD apply + FD steps + write-back */
     RFIM_KERNEL_TD_WIDE_F32 = 4, /* float32 rows outside the fast window */
     RFIM_KERNEL_FD_WIDE_F32 = 5, /* float32 time samples outside the fast window */
-    RFIM_KERNEL_KINDS = 6
+    RFIM_KERNEL_TD_TWO_F32 = 6,  /* float32 rows needing a second fixed-point window */
+    RFIM_KERNEL_FD_TWO_F32 = 7,  /* float32 time samples needing a second window */
+    RFIM_KERNEL_KINDS = 8
 } rfim_kernel_kind;
 
 /* Per-kernel timing of a plan (Section V-B reports execution time averaged

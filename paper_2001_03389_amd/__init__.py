@@ -23,9 +23,11 @@ RFIM_REPLACE_MEAN, RFIM_REPLACE_MEDIAN = 0, 1
 RFIM_TD, RFIM_FD = 0, 1
 RFIM_KERNEL_TD_ROWS_U8, RFIM_KERNEL_FUSED_U8 = 0, 1
 RFIM_KERNEL_TD_ROWS_F32, RFIM_KERNEL_FUSED_F32, RFIM_KERNEL_TD_WIDE_F32, RFIM_KERNEL_FD_WIDE_F32 = 2, 3, 4, 5
+RFIM_KERNEL_TD_TWO_F32, RFIM_KERNEL_FD_TWO_F32 = 6, 7
 KERNEL_NAMES = {RFIM_KERNEL_TD_ROWS_U8: "k_td_rows_u8", RFIM_KERNEL_FUSED_U8: "k_fused_u8",
                 RFIM_KERNEL_TD_ROWS_F32: "k_td_rows_f32", RFIM_KERNEL_FUSED_F32: "k_fused_f32",
-                RFIM_KERNEL_TD_WIDE_F32: "k_td_wide_f32", RFIM_KERNEL_FD_WIDE_F32: "k_fd_wide_f32"}
+                RFIM_KERNEL_TD_WIDE_F32: "k_td_wide_f32", RFIM_KERNEL_FD_WIDE_F32: "k_fd_wide_f32",
+                RFIM_KERNEL_TD_TWO_F32: "k_td_two_f32", RFIM_KERNEL_FD_TWO_F32: "k_fd_two_f32"}
 
 
 class RfimError(RuntimeError):

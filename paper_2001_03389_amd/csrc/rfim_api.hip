@@ -344,6 +344,7 @@ struct LaunchPlan {
     int64_t f32_rows = 0, f32_cols = 0, f32_maxC = 0;
     // workspace layout (byte offsets)
     size_t off_u8rec = 0, off_f32rec = 0, off_wide = 0, off_tditems = 0, off_fditems = 0;
+    size_t off_tdtiny = 0, off_fdtiny = 0;
     size_t count_bytes = 0, work_bytes = 0;
 };
 
@@ -458,7 +459,9 @@ rfim_status make_launch_plan(const rfim_beam* beams, int32_t nbeams, const rfim_
     lp->off_wide = lp->off_f32rec + al((size_t)lp->f32_rows * std::max(1, lp->max_td) * 16);
     lp->off_tditems = lp->off_wide + (lp->f32_beams.empty() ? 0 : 256);
     lp->off_fditems = lp->off_tditems + al((size_t)lp->f32_rows * 8);
-    lp->work_bytes = lp->off_fditems + al((size_t)lp->f32_cols * 8);
+    lp->off_tdtiny = lp->off_fditems + al((size_t)lp->f32_cols * 8);
+    lp->off_fdtiny = lp->off_tdtiny + al((size_t)lp->f32_rows * 8);
+    lp->work_bytes = lp->off_fdtiny + al((size_t)lp->f32_cols * 8);
     return RFIM_OK;
 }
 
@@ -475,8 +478,8 @@ rfim_status dev_err(hipError_t e) {
 // once for a captured graph), then enqueued on one stream.
 // ---------------------------------------------------------------------------
 enum Op {
-    OP_ZERO_COUNTS, OP_TD_U8, OP_FUSED_U8, OP_ZERO_WIDE, OP_TD_F32, OP_LIST_ALL, OP_TD_WIDE,
-    OP_FUSED_F32, OP_FD_WIDE
+    OP_ZERO_COUNTS, OP_TD_U8, OP_FUSED_U8, OP_ZERO_WIDE, OP_TD_F32, OP_TD_TWO, OP_LIST_ALL, OP_TD_WIDE,
+    OP_FUSED_F32, OP_FD_TWO, OP_FD_WIDE
 };
 
 struct Launch {
@@ -578,6 +581,8 @@ void build_f32(const rfim_beam* beams, const LaunchPlan& lp, Program& pg) {
             d.rec0 = rows;
             d.cidx = lp.f32_beams[j];
             d.pad = j;
+            d.Tt = lp.f_shape[si][j].B;     // the two-window FD kernel's shape
+            d.Cp = lp.f_shape[si][j].bpl;
             rows += d.C;
             cols += d.T;
             pg.blob.push_back(d);
@@ -608,6 +613,14 @@ void build_f32(const rfim_beam* beams, const LaunchPlan& lp, Program& pg) {
                 L.total = row;
                 L.a = sh[0];
                 L.b = sh[1];
+                pg.launches.push_back(L);
+            }
+            {
+                Launch L;   // rows with values below the first window
+                L.op = OP_TD_TWO;
+                L.seg = sidx;
+                L.table = all;
+                L.a = (int)std::min<int64_t>(rows, 256);
                 pg.launches.push_back(L);
             }
             for (int j = 0; j < nf; j++) {
@@ -658,6 +671,21 @@ void build_f32(const rfim_beam* beams, const LaunchPlan& lp, Program& pg) {
             pg.launches.push_back(L);
         }
         if (seg.n_fd > 0) {
+            for (auto& fsh : fd_shapes) {
+                if (!fsh[0]) continue;
+                bool any = false;
+                for (int j = 0; j < nf; j++)
+                    any |= lp.f_shape[si][j].B == fsh[0] && lp.f_shape[si][j].bpl == fsh[1];
+                if (!any) continue;
+                Launch L;   // time samples with values below the first window
+                L.op = OP_FD_TWO;
+                L.seg = sidx;
+                L.table = all;
+                L.a = (int)std::min<int64_t>((cols + 3) / 4, 512);
+                L.b = fsh[0];
+                L.nbeams = fsh[1];
+                pg.launches.push_back(L);
+            }
             Launch W;
             W.op = OP_FD_WIDE;
             W.seg = sidx;
@@ -692,6 +720,10 @@ rfim_status enqueue(const Program& pg, const LaunchPlan& lp, const DevBeam* d_bl
     unsigned* wide_fd_n = (unsigned*)(wbase + lp.off_wide + 8);
     int2* td_items = (int2*)(wbase + lp.off_tditems);
     int2* fd_items = (int2*)(wbase + lp.off_fditems);
+    unsigned* tiny_td_n = (unsigned*)(wbase + lp.off_wide + 16);
+    unsigned* tiny_fd_n = (unsigned*)(wbase + lp.off_wide + 24);
+    int2* td_tiny = (int2*)(wbase + lp.off_tdtiny);
+    int2* fd_tiny = (int2*)(wbase + lp.off_fdtiny);
     for (const Launch& L : pg.launches) {
         const DevBeam* tab = L.table >= 0 ? d_blob + L.table : nullptr;
         const Segment& seg = pg.segs[L.seg >= 0 ? L.seg : 0];
@@ -711,12 +743,24 @@ rfim_status enqueue(const Program& pg, const LaunchPlan& lp, const DevBeam* d_bl
                 });
                 break;
             case OP_ZERO_WIDE:
-                e = launch_zero_u64((unsigned long long*)wide_td_n, 2, stream);
+                e = launch_zero_u64((unsigned long long*)wide_td_n, 4, stream);
                 break;
             case OP_TD_F32:
                 e = ws.timed_launch(RFIM_KERNEL_TD_ROWS_F32, stream, [&] {
-                    return launch_td_rows_f32(tab, L.nbeams, L.total, L.a, L.b, seg, frec, wide_td_n, td_items,
-                                              counts, 8, stream);
+                    return launch_td_rows_f32(tab, L.nbeams, L.total, L.a, L.b, seg, frec, tiny_td_n, td_tiny,
+                                              wide_td_n, td_items, counts, 8, stream);
+                });
+                break;
+            case OP_TD_TWO:
+                e = ws.timed_launch(RFIM_KERNEL_TD_TWO_F32, stream, [&] {
+                    return launch_td_two_f32(tab, tiny_td_n, td_tiny, L.a, seg, frec, wide_td_n, td_items, counts,
+                                             8, stream);
+                });
+                break;
+            case OP_FD_TWO:
+                e = ws.timed_launch(RFIM_KERNEL_FD_TWO_F32, stream, [&] {
+                    return launch_fd_two_f32(tab, tiny_fd_n, fd_tiny, L.a, L.b, L.nbeams, seg, wide_fd_n, fd_items,
+                                             counts, 8, stream);
                 });
                 break;
             case OP_LIST_ALL:
@@ -729,8 +773,8 @@ rfim_status enqueue(const Program& pg, const LaunchPlan& lp, const DevBeam* d_bl
                 break;
             case OP_FUSED_F32:
                 e = ws.timed_launch(RFIM_KERNEL_FUSED_F32, stream, [&] {
-                    return launch_fused_f32(tab, L.nbeams, L.total, L.a, L.b, seg, frec, L.lds, wide_fd_n,
-                                            fd_items, counts, 8, stream);
+                    return launch_fused_f32(tab, L.nbeams, L.total, L.a, L.b, seg, frec, L.lds, tiny_fd_n, fd_tiny,
+                                            wide_fd_n, fd_items, counts, 8, stream);
                 });
                 break;
             case OP_FD_WIDE:

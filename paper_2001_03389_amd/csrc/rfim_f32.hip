@@ -87,6 +87,10 @@ __device__ inline bool below_window(uint32_t bits, uint32_t thr) {
 }
 
 __device__ inline uint32_t window_thr(int EM) { return EM - 24 >= 1 ? (uint32_t)(EM - 24) << 23 : 0u; }
+// bits of the smallest magnitude inside the second window (24 exponents lower)
+__device__ inline uint32_t window_thr2(int EM) { return EM - 48 >= 1 ? (uint32_t)(EM - 48) << 23 : 0u; }
+
+constexpr u128 kZcap2 = (u128)1 << 94;   // beyond every |n*a - S| in second-window units
 
 // ---- work-group radix select (TD median) ---------------------------------
 
@@ -141,33 +145,46 @@ __device__ inline uint32_t wg_select_key(uint64_t rank, uint32_t* s_hist, uint32
 // ---------------------------------------------------------------------------
 // TD: one work-group per row, row resident in registers
 // ---------------------------------------------------------------------------
-template <int NT, int VPT>
-__global__ __launch_bounds__(NT) void k_td_rows_f32(const DevBeam* __restrict__ beams, int nbeams, Segment seg,
-                                                    float4* __restrict__ rec, unsigned* __restrict__ wide_n,
-                                                    int2* __restrict__ wide_items,
-                                                    unsigned long long* __restrict__ counts, int count_stride) {
+// All TD steps of the run for row c of beam bm, by the whole work-group.
+// VL of each lane's VPT values live in LDS (rows too long for the register
+// file alone), the other VR = VPT - VL in registers.  TWO = false: the first
+// window only; a row with values below it goes to the two-window list
+// (tiny_*), whose kernel runs this body with TWO = true; a row with values
+// below the second window goes to the wide list.
+template <int NT, int VPT, int VL, bool TWO>
+__device__ inline void td_row_f32(const DevBeam& bm, int64_t c, const Segment& seg, float4* __restrict__ rec,
+                                  unsigned* __restrict__ tiny_n, int2* __restrict__ tiny_items,
+                                  unsigned* __restrict__ wide_n, int2* __restrict__ wide_items,
+                                  unsigned long long* __restrict__ counts, int count_stride) {
     constexpr int NW = NT / 64;
+    constexpr int VR = VPT - VL;
     __shared__ uint32_t s_hist[NW * 256];
+    __shared__ float s_row[VL > 0 ? VL * NT : 1];
     __shared__ uint32_t s_tot[NW], s_sel[2];
-    __shared__ int64_t s_S[NW];
-    __shared__ uint64_t s_Q[NW][2];
+    __shared__ int64_t s_S[NW], s_S1[NW];
+    __shared__ uint64_t s_Q[NW][2], s_Q1[NW][2];
     __shared__ uint32_t s_u[NW][2];
     __shared__ float s_dec[3];
     __shared__ int s_bad;
     __shared__ uint32_t s_cnt[kMaxSteps];
+    // wave 0 parks its row values here while it decides a step, so that the
+    // decision's wide-integer temporaries reuse their registers
+    __shared__ float s_park[64 * VR];
 
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    const int64_t g = blockIdx.x;
-    const int b = find_beam_by_row(beams, nbeams, g);
-    const DevBeam& bm = beams[b];
-    const int64_t c = g - bm.row0;
     const int64_t T = bm.T;
     const float* row = (const float*)bm.in + c * bm.stride;
     const bool vec = (VPT % 4 == 0) && ((((uintptr_t)row) & 15) == 0);
 
     // values of this lane: index i*NT + tid (scalar) or 4*((i/4)*NT + tid) + i%4
     // (16-byte loads); both increase with i, so the valid ones are a prefix
-    float v[VPT];
+    float v[VR];
+    // value i of this lane (i a compile-time constant after unrolling)
+    auto get = [&](int i) -> float { return i < VR ? v[i < VR ? i : 0] : s_row[(i - VR) * NT + tid]; };
+    auto set = [&](int i, float x) {
+        if (i < VR) v[i < VR ? i : 0] = x;
+        else s_row[(i - VR) * NT + tid] = x;
+    };
     int nv = 0;
     if (vec) {
 #pragma unroll
@@ -175,13 +192,13 @@ __global__ __launch_bounds__(NT) void k_td_rows_f32(const DevBeam* __restrict__ 
             const int64_t i0 = ((int64_t)i4 * NT + tid) * 4;
             if (i0 + 3 < T) {
                 const float4 q = *(const float4*)(row + i0);
-                v[4 * i4] = q.x;
-                v[4 * i4 + 1] = q.y;
-                v[4 * i4 + 2] = q.z;
-                v[4 * i4 + 3] = q.w;
+                set(4 * i4, q.x);
+                set(4 * i4 + 1, q.y);
+                set(4 * i4 + 2, q.z);
+                set(4 * i4 + 3, q.w);
             } else {
 #pragma unroll
-                for (int j = 0; j < 4; j++) v[4 * i4 + j] = i0 + j < T ? row[i0 + j] : 0.0f;
+                for (int j = 0; j < 4; j++) set(4 * i4 + j, i0 + j < T ? row[i0 + j] : 0.0f);
             }
             const int64_t rem = T - i0;
             nv += rem >= 4 ? 4 : (rem > 0 ? (int)rem : 0);
@@ -190,7 +207,7 @@ __global__ __launch_bounds__(NT) void k_td_rows_f32(const DevBeam* __restrict__ 
 #pragma unroll
         for (int i = 0; i < VPT; i++) {
             const int64_t idx = (int64_t)i * NT + tid;
-            v[i] = idx < T ? row[idx] : 0.0f;
+            set(i, idx < T ? row[idx] : 0.0f);
             nv += idx < T ? 1 : 0;
         }
     }
@@ -199,7 +216,7 @@ __global__ __launch_bounds__(NT) void k_td_rows_f32(const DevBeam* __restrict__ 
     uint32_t emax = 0, tmin = 0xFFFFFFFFu;
 #pragma unroll
     for (int i = 0; i < VPT; i++) {
-        const uint32_t bb = __float_as_uint(v[i]) & 0x7FFFFFFFu;   // padding is +0
+        const uint32_t bb = __float_as_uint(get(i)) & 0x7FFFFFFFu;   // padding is +0
         emax = max(emax, bb);
         tmin = min(tmin, bb - 1u);                                  // 0 wraps: ignored
     }
@@ -219,24 +236,48 @@ __global__ __launch_bounds__(NT) void k_td_rows_f32(const DevBeam* __restrict__ 
         tmin = min(tmin, s_u[w][1]);
     }
     const int EM = f32_E(emax);
-    const uint32_t thr = window_thr(EM);
-    bool bad = tmin != 0xFFFFFFFFu && tmin + 1u < thr;
-    const double sc = ldexp(1.0, 174 - EM);
-    const int e = EM - 174;
+    const uint32_t thr = window_thr(EM), thr2 = window_thr2(EM);
+    // values below the first window use the second; below that, the wide path
+    const bool has_tiny = tmin != 0xFFFFFFFFu && tmin + 1u < thr;
+    bool bad = tmin != 0xFFFFFFFFu && tmin + 1u < thr2;
+    bool to_two = !TWO && has_tiny && !bad;   // hand over to the two-window kernel
+    const bool tiny = TWO;
+    const double sc = ldexp(1.0, 174 - EM), sc2 = ldexp(1.0, 198 - EM);
+    const int e = EM - 174, e2 = EM - 198;
     const uint32_t n = (uint32_t)T;
 
-    for (int j = 0; j < seg.n_td && !bad; j++) {
+    for (int j = 0; j < seg.n_td && !bad && !to_two; j++) {
         const SegStep& st = seg.td[j];
-        // exact window sums
-        int64_t S = 0;
-        u128 Q = 0;
+        // exact window sums (both windows when the row has values below the first)
+        int64_t S = 0, S1 = 0;
+        u128 Q = 0, Q1 = 0;
+        if (!tiny) {
 #pragma unroll
-        for (int i0 = 0; i0 < VPT; i0 += 32) {
-            WinAcc w{0.0, 0.0, 0.0};
+            for (int i0 = 0; i0 < VPT; i0 += 32) {
+                WinAcc w{0.0, 0.0, 0.0};
 #pragma unroll
-            for (int i = i0; i < (i0 + 32 < VPT ? i0 + 32 : VPT); i++) winacc_add(w, (double)v[i] * sc);
-            S += (int64_t)w.s;
-            Q += winacc_q(w);
+                for (int i = i0; i < (i0 + 32 < VPT ? i0 + 32 : VPT); i++) winacc_add(w, (double)get(i) * sc);
+                S += (int64_t)w.s;
+                Q += winacc_q(w);
+            }
+        } else {
+#pragma unroll 1
+            for (int i0 = 0; i0 < VPT; i0 += 32) {
+                WinAcc w{0.0, 0.0, 0.0}, w1{0.0, 0.0, 0.0};
+#pragma unroll
+                for (int i = i0; i < (i0 + 32 < VPT ? i0 + 32 : VPT); i++) {
+                    const float x = get(i);
+                    const bool lo = below_window(__float_as_uint(x), thr);
+                    winacc_add(w, lo ? 0.0 : (double)x * sc);
+                    winacc_add(w1, lo ? (double)x * sc2 : 0.0);
+                }
+                S += (int64_t)w.s;
+                Q += winacc_q(w);
+                S1 += (int64_t)w1.s;
+                Q1 += winacc_q(w1);
+            }
+            S1 = wave_add_i64(S1);
+            Q1 = group_add_u128(Q1, 64);
         }
         S = wave_add_i64(S);
         Q = group_add_u128(Q, 64);
@@ -244,6 +285,9 @@ __global__ __launch_bounds__(NT) void k_td_rows_f32(const DevBeam* __restrict__ 
             s_S[wave] = S;
             s_Q[wave][0] = (uint64_t)Q;
             s_Q[wave][1] = (uint64_t)(Q >> 64);
+            s_S1[wave] = S1;
+            s_Q1[wave][0] = (uint64_t)Q1;
+            s_Q1[wave][1] = (uint64_t)(Q1 >> 64);
         }
         __syncthreads();
         float med = 0.0f;
@@ -251,40 +295,61 @@ __global__ __launch_bounds__(NT) void k_td_rows_f32(const DevBeam* __restrict__ 
             const uint32_t key = wg_select_key<NT>((uint64_t)(n - 1) / 2, s_hist, s_tot, s_sel, [&](auto&& add) {
 #pragma unroll
                 for (int i = 0; i < VPT; i++)
-                    if (i < nv) add(f32_key(__float_as_uint(v[i])));
+                    if (i < nv) add(f32_key(__float_as_uint(get(i))));
             });
             med = __uint_as_float(key_f32(key));
         }
         if (wave == 0) {
-            i128 St = 0;
-            u128 Qt = 0;
+#pragma unroll
+            for (int i = 0; i < VR; i++) s_park[i * 64 + lane] = v[i];
+            i128 St = 0, St1 = 0;
+            u128 Qt = 0, Qt1 = 0;
             for (int w = 0; w < NW; w++) {
                 St += s_S[w];
                 Qt += ((u128)s_Q[w][1] << 64) | s_Q[w][0];
+                St1 += s_S1[w];
+                Qt1 += ((u128)s_Q1[w][1] << 64) | s_Q1[w][0];
             }
-            const u128 Sa = St < 0 ? (u128)(-St) : (u128)St;
-            const u128 D = (u128)n * Qt - Sa * Sa;
-            const u128 z = zmax_k2(1, D, st.kx, kZcap);
-            const float H = f32_round_ratio(St + (i128)z, n, e, kRD);
-            const float Lo = f32_round_ratio(St - (i128)z, n, e, kRU);
-            const float r = st.replace == RFIM_REPLACE_MEDIAN ? med : f32_round_ratio(St, n, e, kRN);
+            float H, Lo, rm;
+            if (!TWO) {
+                const u128 Sa = St < 0 ? (u128)(-St) : (u128)St;
+                const u128 D = (u128)n * Qt - Sa * Sa;
+                const u128 z = zmax_k2(1, D, st.kx, kZcap);
+                H = f32_round_ratio(St + (i128)z, n, e, kRD);
+                Lo = f32_round_ratio(St - (i128)z, n, e, kRU);
+                rm = f32_round_ratio(St, n, e, kRN);
+            } else {
+                // units of the second window: S = S0 * 2^24 + S1, Q = Q0 * 2^48 + Q1
+                const i128 Sc = St * ((i128)1 << 24) + St1;
+                const U512 D = d_combine(n, q_combine(Qt, Qt1), Sc);
+                const u128 z = zmax_k2w(1, D, st.kx, kZcap2);
+                H = f32_round_ratio(Sc + (i128)z, n, e2, kRD);
+                Lo = f32_round_ratio(Sc - (i128)z, n, e2, kRU);
+                rm = f32_round_ratio(Sc, n, e2, kRN);
+            }
+            const float r = st.replace == RFIM_REPLACE_MEDIAN ? med : rm;
             if (lane == 0) {
                 s_dec[0] = Lo;
                 s_dec[1] = H;
                 s_dec[2] = r;
-                if (below_window(__float_as_uint(r), thr)) s_bad = 1;
+                if (below_window(__float_as_uint(r), thr2)) s_bad = 1;
+                else if (!TWO && below_window(__float_as_uint(r), thr)) s_bad = 2;
                 rec[(bm.rec0 + c) * seg.n_td + j] = make_float4(Lo, H, r, 0.0f);
             }
+#pragma unroll
+            for (int i = 0; i < VR; i++) v[i] = s_park[i * 64 + lane];
         }
         __syncthreads();
         const float Lo = s_dec[0], H = s_dec[1], r = s_dec[2];
-        bad = s_bad != 0;
+        bad = s_bad == 1;
+        to_two = s_bad == 2;   // a replacement below the first window joins the data
         uint32_t cnt = 0;
 #pragma unroll
         for (int i = 0; i < VPT; i++) {
             if (i < nv) {
-                const bool f = v[i] < Lo || v[i] > H;
-                v[i] = f ? r : v[i];
+                const float x = get(i);
+                const bool f = x < Lo || x > H;
+                if (f) set(i, r);
                 cnt += f ? 1u : 0u;
             }
         }
@@ -292,15 +357,43 @@ __global__ __launch_bounds__(NT) void k_td_rows_f32(const DevBeam* __restrict__ 
         if (lane == 0 && cnt) atomicAdd(&s_cnt[j], cnt);
     }
     __syncthreads();
-    if (bad) {
+    if (bad || to_two) {
         if (tid == 0) {
-            const unsigned slot = atomicAdd(wide_n, 1u);
-            wide_items[slot] = make_int2(bm.pad, (int)c);
+            const unsigned slot = atomicAdd(bad ? wide_n : tiny_n, 1u);
+            (bad ? wide_items : tiny_items)[slot] = make_int2(bm.pad, (int)c);
         }
-        return;
-    }
-    if (counts && tid < seg.n_td && s_cnt[tid] && seg.td[tid].bit >= 0)
+    } else if (counts && tid < seg.n_td && s_cnt[tid] && seg.td[tid].bit >= 0) {
         atomicAdd(&counts[(int64_t)bm.cidx * count_stride + seg.td[tid].bit], (unsigned long long)s_cnt[tid]);
+    }
+    __syncthreads();   // the work-group's LDS is reused by the next row
+}
+
+template <int NT, int VPT, int VL>
+__global__ __launch_bounds__(NT) void k_td_rows_f32(const DevBeam* __restrict__ beams, int nbeams, Segment seg,
+                                                    float4* __restrict__ rec, unsigned* __restrict__ tiny_n,
+                                                    int2* __restrict__ tiny_items, unsigned* __restrict__ wide_n,
+                                                    int2* __restrict__ wide_items,
+                                                    unsigned long long* __restrict__ counts, int count_stride) {
+    const int64_t g = blockIdx.x;
+    const int b = find_beam_by_row(beams, nbeams, g);
+    const DevBeam& bm = beams[b];
+    td_row_f32<NT, VPT, VL, false>(bm, g - bm.row0, seg, rec, tiny_n, tiny_items, wide_n, wide_items, counts,
+                                   count_stride);
+}
+
+// Rows the fast kernel listed (values below its window): both windows, any
+// row length the largest shape holds; a persistent grid walks the list.
+__global__ __launch_bounds__(1024) void k_td_two_f32(const DevBeam* __restrict__ all, Segment seg,
+                                                     float4* __restrict__ rec, const unsigned* __restrict__ tiny_n,
+                                                     const int2* __restrict__ tiny_items,
+                                                     unsigned* __restrict__ wide_n, int2* __restrict__ wide_items,
+                                                     unsigned long long* __restrict__ counts, int count_stride) {
+    const unsigned n = *tiny_n;
+    for (unsigned it = blockIdx.x; it < n; it += gridDim.x) {
+        const int2 item = tiny_items[it];
+        td_row_f32<1024, 64, 32, true>(all[item.x], item.y, seg, rec, nullptr, nullptr, wide_n, wide_items, counts,
+                                       count_stride);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -344,11 +437,137 @@ __device__ inline float bin_median(const float (&x)[B]) {
     return __uint_as_float(key_f32(k[(B - 1) / 2]));
 }
 
+// Sum over G lanes (xor groups) of the low four 64-bit limbs of a U512.
+__device__ inline U512 group_add_u256(U512 v, int G) {
+    for (int o = 1; o < G; o <<= 1) {
+        uint64_t w[4];
+#pragma unroll
+        for (int i = 0; i < 4; i++) w[i] = __shfl_xor(v.w[i], o, 64);
+        u128 c = 0;
+#pragma unroll
+        for (int i = 0; i < 4; i++) {
+            c += (u128)v.w[i] + w[i];
+            v.w[i] = (uint64_t)c;
+            c >>= 64;
+        }
+    }
+    return v;
+}
+
+// Every FD step of the run on one time sample held by a group of G2 lanes:
+// lane's bins are x[kk] (B values each, act[kk] when the bin exists), flag
+// bytes collect in fw, per-step counts in lc (16 bits per step).  TWO:
+// statistics in both windows.  Returns 0 when done, 1 when the time sample
+// needs the wide path (values below the last window), 2 (TWO = false only)
+// when it needs the two-window kernel; x is then not final.
+template <int B, int BPL, bool TWO>
+__device__ inline int fd_column_f32(float (&x)[BPL][B], uint32_t (&fw)[BPL][B / 4], const bool (&act)[BPL], int G2,
+                                    uint32_t C, const Segment& seg, uint64_t lc[2]) {
+    uint32_t emax = 0, tmin = 0xFFFFFFFFu;
+#pragma unroll
+    for (int kk = 0; kk < BPL; kk++)
+#pragma unroll
+        for (int j = 0; j < B; j++) {
+            const uint32_t bb = __float_as_uint(x[kk][j]) & 0x7FFFFFFFu;
+            emax = max(emax, bb);
+            tmin = min(tmin, bb - 1u);
+        }
+    emax = group_max_u32(emax, G2);
+    tmin = group_min_u32(tmin, G2);
+    const int EM = f32_E(emax);
+    const uint32_t thr = window_thr(EM), thr2 = window_thr2(EM);
+    if (tmin != 0xFFFFFFFFu && tmin + 1u < thr2) return 1;
+    if (!TWO && tmin != 0xFFFFFFFFu && tmin + 1u < thr) return 2;
+    const double sc = ldexp(1.0, 174 - EM), sc2 = ldexp(1.0, 198 - EM);
+    const int e = TWO ? EM - 198 : EM - 174;
+    lc[0] = lc[1] = 0;
+    for (int s = 0; s < seg.n_fd; s++) {
+        const SegStep& st = seg.fd[s];
+        i128 S[BPL];
+        u128 z;
+        if (!TWO) {
+            u128 V = 0;
+#pragma unroll
+            for (int kk = 0; kk < BPL; kk++) {
+                int64_t Sb = 0;
+                u128 Qb = 0;
+#pragma unroll
+                for (int j0 = 0; j0 < B; j0 += 32) {
+                    WinAcc w{0.0, 0.0, 0.0};
+#pragma unroll
+                    for (int j = j0; j < (j0 + 32 < B ? j0 + 32 : B); j++) winacc_add(w, (double)x[kk][j] * sc);
+                    Sb += (int64_t)w.s;
+                    Qb += winacc_q(w);
+                }
+                S[kk] = Sb;
+                const u128 Sa = Sb < 0 ? (u128)(-(i128)Sb) : (u128)Sb;
+                if (act[kk]) V += (u128)B * Qb - Sa * Sa;
+            }
+            V = group_add_u128(V, G2);
+            // sum over the time sample of Z_c^2 = B * sum_b (B*Q_b - S_b^2)
+            z = zmax_k2(C, (u128)B * V, st.kx, kZcap);
+        } else {
+            U512 V = u512_from(0);
+#pragma unroll
+            for (int kk = 0; kk < BPL; kk++) {
+                int64_t S0 = 0, S1 = 0;
+                u128 Q0 = 0, Q1 = 0;
+#pragma unroll
+                for (int j0 = 0; j0 < B; j0 += 32) {
+                    WinAcc w{0.0, 0.0, 0.0}, w1{0.0, 0.0, 0.0};
+#pragma unroll
+                    for (int j = j0; j < (j0 + 32 < B ? j0 + 32 : B); j++) {
+                        const bool lo = below_window(__float_as_uint(x[kk][j]), thr);
+                        winacc_add(w, lo ? 0.0 : (double)x[kk][j] * sc);
+                        winacc_add(w1, lo ? (double)x[kk][j] * sc2 : 0.0);
+                    }
+                    S0 += (int64_t)w.s;
+                    Q0 += winacc_q(w);
+                    S1 += (int64_t)w1.s;
+                    Q1 += winacc_q(w1);
+                }
+                // units of the second window: S = S0 * 2^24 + S1, Q = Q0 * 2^48 + Q1
+                S[kk] = (i128)S0 * ((i128)1 << 24) + S1;
+                if (act[kk]) V = u512_add(V, d_combine(B, q_combine(Q0, Q1), S[kk]));
+            }
+            V = group_add_u256(V, G2);
+            z = zmax_k2w(C, u512_mul_u128(V, (u128)B), st.kx, kZcap2);
+        }
+        const int bit = st.bit;
+        uint32_t bad = 0;
+#pragma unroll
+        for (int kk = 0; kk < BPL; kk++) {
+            if (!act[kk]) continue;
+            const float H = f32_round_ratio(S[kk] + (i128)z, B, e, kRD);
+            const float Lo = f32_round_ratio(S[kk] - (i128)z, B, e, kRU);
+            uint64_t fm = 0;
+#pragma unroll
+            for (int j = 0; j < B; j++) fm |= (uint64_t)(x[kk][j] < Lo || x[kk][j] > H) << j;
+            if (!fm) continue;
+            const float r = st.replace == RFIM_REPLACE_MEDIAN ? bin_median<B>(x[kk])
+                                                              : f32_round_ratio(S[kk], B, e, kRN);
+            if (below_window(__float_as_uint(r), thr2)) bad |= 1u;
+            else if (!TWO && below_window(__float_as_uint(r), thr)) bad |= 2u;
+#pragma unroll
+            for (int j = 0; j < B; j++) {
+                const bool f = (fm >> j) & 1;
+                x[kk][j] = f ? r : x[kk][j];
+                if (bit >= 0 && f) fw[kk][j / 4] |= (1u << bit) << (8 * (j % 4));
+            }
+            if (bit >= 0) lc[bit >> 2] += (uint64_t)__popcll(fm) << (16 * (bit & 3));
+        }
+        bad = group_or_u32(bad, G2);
+        if (bad) return (bad & 1u) ? 1 : 2;
+    }
+    return 0;
+}
+
 // All FD steps for the time samples of this wave.  B channels per bin, BPL
 // bins per lane, groups of G2 lanes per time sample.
 template <int B, int BPL>
 __device__ void fd_fast_f32(const F32Tile& k, const Segment& seg, float* tile, uint8_t* ftile, bool want_flags,
-                            unsigned* wide_n, int2* wide_items, int gidx, uint64_t cntp[2]) {
+                            unsigned* tiny_n, int2* tiny_items, unsigned* wide_n, int2* wide_items, int gidx,
+                            uint64_t cntp[2]) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     constexpr int NW = kF32Block / 64;
     const int nbins = (int)(k.C / B);
@@ -379,75 +598,15 @@ __device__ void fd_fast_f32(const F32Tile& k, const Segment& seg, float* tile, u
 #pragma unroll
             for (int j = 0; j < B / 4; j++) fw[kk][j] = 0;
         }
-        // window of the time sample
-        uint32_t emax = 0, tmin = 0xFFFFFFFFu;
-#pragma unroll
-        for (int kk = 0; kk < BPL; kk++)
-#pragma unroll
-            for (int j = 0; j < B; j++) {
-                const uint32_t bb = __float_as_uint(x[kk][j]) & 0x7FFFFFFFu;
-                emax = max(emax, bb);
-                tmin = min(tmin, bb - 1u);
-            }
-        emax = group_max_u32(emax, G2);
-        tmin = group_min_u32(tmin, G2);
-        const int EM = f32_E(emax);
-        const uint32_t thr = window_thr(EM);
-        uint32_t bad = (tmin != 0xFFFFFFFFu && tmin + 1u < thr) ? 1u : 0u;
-        const double sc = ldexp(1.0, 174 - EM);
-        const int e = EM - 174;
-        uint64_t lc[2] = {0, 0};   // this time sample's counts, 16 bits per step
-        for (int s = 0; s < seg.n_fd && !bad; s++) {
-            const SegStep& st = seg.fd[s];
-            int64_t S[BPL];
-            u128 V = 0;
-#pragma unroll
-            for (int kk = 0; kk < BPL; kk++) {
-                int64_t Sb = 0;
-                u128 Qb = 0;
-#pragma unroll
-                for (int j0 = 0; j0 < B; j0 += 32) {
-                    WinAcc w{0.0, 0.0, 0.0};
-#pragma unroll
-                    for (int j = j0; j < (j0 + 32 < B ? j0 + 32 : B); j++) winacc_add(w, (double)x[kk][j] * sc);
-                    Sb += (int64_t)w.s;
-                    Qb += winacc_q(w);
-                }
-                S[kk] = Sb;
-                const u128 Sa = Sb < 0 ? (u128)(-(i128)Sb) : (u128)Sb;
-                if (act[kk]) V += (u128)B * Qb - Sa * Sa;
-            }
-            V = group_add_u128(V, G2);
-            // sum over the time sample of Z_c^2 = B * sum_b (B*Q_b - S_b^2)
-            const u128 z = zmax_k2(C, (u128)B * V, st.kx, kZcap);
-            const int bit = st.bit;
-#pragma unroll
-            for (int kk = 0; kk < BPL; kk++) {
-                if (!act[kk]) continue;
-                const float H = f32_round_ratio((i128)S[kk] + (i128)z, B, e, kRD);
-                const float Lo = f32_round_ratio((i128)S[kk] - (i128)z, B, e, kRU);
-                uint64_t fm = 0;
-#pragma unroll
-                for (int j = 0; j < B; j++) fm |= (uint64_t)(x[kk][j] < Lo || x[kk][j] > H) << j;
-                if (!fm) continue;
-                const float r = st.replace == RFIM_REPLACE_MEDIAN ? bin_median<B>(x[kk])
-                                                                  : f32_round_ratio((i128)S[kk], B, e, kRN);
-                if (below_window(__float_as_uint(r), thr)) bad = 1u;
-#pragma unroll
-                for (int j = 0; j < B; j++) {
-                    const bool f = (fm >> j) & 1;
-                    x[kk][j] = f ? r : x[kk][j];
-                    if (bit >= 0 && f) fw[kk][j / 4] |= (1u << bit) << (8 * (j % 4));
-                }
-                if (bit >= 0) lc[bit >> 2] += (uint64_t)__popcll(fm) << (16 * (bit & 3));
-            }
-            bad = group_or_u32(bad, G2);
-        }
+        uint64_t lc[2];
+        const int res = fd_column_f32<B, BPL, false>(x, fw, act, G2, C, seg, lc);
         if (!colok) continue;
-        if (bad) {
+        if (res) {
+            // the tile keeps this time sample's post-TD values for the other kernel
             if (gl == 0) {
-                const unsigned slot = atomicAdd(wide_n, 1u);
-                wide_items[slot] = make_int2(gidx, (int)(k.t0 + t));
+                unsigned* cnt = res == 1 ? wide_n : tiny_n;
+                const unsigned slot = atomicAdd(cnt, 1u);
+                (res == 1 ? wide_items : tiny_items)[slot] = make_int2(gidx, (int)(k.t0 + t));
             }
             continue;
         }
@@ -479,6 +638,7 @@ template <int B, int BPL>
 __global__ __launch_bounds__(kF32Block) void k_fused_f32(const DevBeam* __restrict__ beams, int nbeams,
                                                          int64_t total_tiles, Segment seg,
                                                          const float4* __restrict__ rec,
+                                                         unsigned* __restrict__ tiny_n, int2* __restrict__ tiny_items,
                                                          unsigned* __restrict__ wide_n, int2* __restrict__ wide_items,
                                                          unsigned long long* __restrict__ counts, int count_stride) {
     extern __shared__ __align__(16) uint8_t lds[];
@@ -583,7 +743,8 @@ __global__ __launch_bounds__(kF32Block) void k_fused_f32(const DevBeam* __restri
     // ---- phase 2: FD steps
     uint64_t cntp[2] = {0, 0};
     if (seg.n_fd > 0) {
-        if constexpr (B > 0) fd_fast_f32<B, BPL>(k, seg, tile, ftile, want_flags, wide_n, wide_items, bm.pad, cntp);
+        if constexpr (B > 0)
+            fd_fast_f32<B, BPL>(k, seg, tile, ftile, want_flags, tiny_n, tiny_items, wide_n, wide_items, bm.pad, cntp);
     }
     __syncthreads();
 
@@ -622,6 +783,71 @@ __global__ __launch_bounds__(kF32Block) void k_fused_f32(const DevBeam* __restri
         }
         __syncthreads();
         if (tid < 8 && s_cnt[tid]) atomicAdd(&counts[(int64_t)bm.cidx * count_stride + tid], s_cnt[tid]);
+    }
+}
+
+// Time samples the fused kernel listed (values below its window): every FD
+// step in both windows, one wave per time sample read from the output (post-TD
+// values), written back with the flag bits ORed in.  Launched once per fast
+// bin shape; items of beams with another shape are left to their launch.
+template <int B, int BPL>
+__global__ __launch_bounds__(kF32Block) void k_fd_two_f32(const DevBeam* __restrict__ all, Segment seg,
+                                                          const unsigned* __restrict__ tiny_n,
+                                                          const int2* __restrict__ tiny_items,
+                                                          unsigned* __restrict__ wide_n, int2* __restrict__ wide_items,
+                                                          unsigned long long* __restrict__ counts, int count_stride) {
+    constexpr int NW = kF32Block / 64;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const unsigned n = *tiny_n;
+    for (unsigned it = blockIdx.x * NW + wave; it < n; it += gridDim.x * NW) {
+        const int2 item = tiny_items[it];
+        const DevBeam& bm = all[item.x];
+        if (bm.Tt != B || bm.Cp != BPL) continue;   // another launch's shape
+        const int64_t t = item.y;
+        const int nbins = (int)(bm.C / B);
+        const int G2 = nbins > 64 ? 64 : pow2_ceil(nbins);
+        float* out = (float*)bm.out;
+        const bool want_flags = seg.flags_mode != 0 && bm.flags != nullptr;
+        float x[BPL][B];
+        uint32_t fw[BPL][B / 4];
+        bool act[BPL];
+#pragma unroll
+        for (int kk = 0; kk < BPL; kk++) {
+            const int bin = lane + 64 * kk;
+            act[kk] = lane < G2 && bin < nbins;
+#pragma unroll
+            for (int j = 0; j < B; j++) x[kk][j] = act[kk] ? out[((int64_t)bin * B + j) * bm.stride + t] : 0.0f;
+#pragma unroll
+            for (int j = 0; j < B / 4; j++) fw[kk][j] = 0;
+        }
+        uint64_t lc[2];
+        const int res = fd_column_f32<B, BPL, true>(x, fw, act, G2, (uint32_t)bm.C, seg, lc);
+        if (res) {
+            if (lane == 0) {
+                const unsigned slot = atomicAdd(wide_n, 1u);
+                wide_items[slot] = make_int2(item.x, (int)t);
+            }
+            continue;
+        }
+#pragma unroll
+        for (int kk = 0; kk < BPL; kk++) {
+            if (!act[kk]) continue;
+            const int bin = lane + 64 * kk;
+#pragma unroll
+            for (int j = 0; j < B; j++) {
+                const int64_t off = ((int64_t)bin * B + j) * bm.stride + t;
+                out[off] = x[kk][j];
+                const uint32_t f = (fw[kk][j / 4] >> (8 * (j % 4))) & 255u;
+                if (want_flags && f) bm.flags[off] |= (uint8_t)f;
+            }
+        }
+        if (counts) {
+            for (int sidx = 0; sidx < 8; sidx++) {
+                const uint32_t v = (uint32_t)((lc[sidx >> 2] >> (16 * (sidx & 3))) & 0xFFFFu);
+                const uint32_t tot = wave_add_u32(v);
+                if (lane == 0 && tot) atomicAdd(&counts[(int64_t)bm.cidx * count_stride + sidx], (unsigned long long)tot);
+            }
+        }
     }
 }
 
@@ -846,36 +1072,38 @@ __global__ void k_list_all(unsigned* __restrict__ wide_n, int2* __restrict__ ite
 // ---------------------------------------------------------------------------
 
 hipError_t launch_td_rows_f32(const DevBeam* d_beams, int nbeams, int64_t total_rows, int nt, int vpt,
-                              const Segment& seg, float4* rec, unsigned* wide_n, int2* wide_items,
-                              unsigned long long* counts, int count_stride, hipStream_t s) {
+                              const Segment& seg, float4* rec, unsigned* tiny_n, int2* tiny_items, unsigned* wide_n,
+                              int2* wide_items, unsigned long long* counts, int count_stride, hipStream_t s) {
     if (total_rows <= 0) return hipSuccess;
     const dim3 grid((unsigned)total_rows);
-#define RFIM_TDF(NT_, VPT_)                                                                           \
-    if (nt == NT_ && vpt == VPT_) {                                                                   \
-        hipLaunchKernelGGL((k_td_rows_f32<NT_, VPT_>), grid, dim3(NT_), 0, s, d_beams, nbeams, seg, rec, \
-                           wide_n, wide_items, counts, count_stride);                                \
-        return hipGetLastError();                                                                     \
+#define RFIM_TDF(NT_, VPT_, VL_)                                                                        \
+    if (nt == NT_ && vpt == VPT_) {                                                                     \
+        hipLaunchKernelGGL((k_td_rows_f32<NT_, VPT_, VL_>), grid, dim3(NT_), 0, s, d_beams, nbeams, seg, rec, \
+                           tiny_n, tiny_items, wide_n, wide_items, counts, count_stride);              \
+        return hipGetLastError();                                                                       \
     }
-    RFIM_TDF(256, 1)
-    RFIM_TDF(256, 4)
-    RFIM_TDF(256, 16)
-    RFIM_TDF(1024, 8)
-    RFIM_TDF(1024, 16)
-    RFIM_TDF(1024, 32)
-    RFIM_TDF(1024, 64)
+    RFIM_TDF(256, 1, 0)
+    RFIM_TDF(256, 4, 0)
+    RFIM_TDF(256, 16, 0)
+    RFIM_TDF(1024, 8, 0)
+    RFIM_TDF(1024, 16, 0)
+    RFIM_TDF(1024, 32, 0)
+    RFIM_TDF(1024, 64, 32)
 #undef RFIM_TDF
     return hipErrorInvalidValue;
 }
 
 hipError_t launch_fused_f32(const DevBeam* d_beams, int nbeams, int64_t total_tiles, int B, int bpl,
-                            const Segment& seg, const float4* rec, size_t lds_bytes, unsigned* wide_n,
-                            int2* wide_items, unsigned long long* counts, int count_stride, hipStream_t s) {
+                            const Segment& seg, const float4* rec, size_t lds_bytes, unsigned* tiny_n,
+                            int2* tiny_items, unsigned* wide_n, int2* wide_items, unsigned long long* counts,
+                            int count_stride, hipStream_t s) {
     if (total_tiles <= 0) return hipSuccess;
     const dim3 grid((unsigned)total_tiles);
 #define RFIM_FF(B_, BPL_)                                                                              \
     if (B == B_ && bpl == BPL_) {                                                                      \
         hipLaunchKernelGGL((k_fused_f32<B_, BPL_>), grid, dim3(kF32Block), lds_bytes, s, d_beams, nbeams, \
-                           total_tiles, seg, rec, wide_n, wide_items, counts, count_stride);           \
+                           total_tiles, seg, rec, tiny_n, tiny_items, wide_n, wide_items, counts,      \
+                           count_stride);                                                              \
         return hipGetLastError();                                                                      \
     }
     RFIM_FF(0, 1)
@@ -887,6 +1115,36 @@ hipError_t launch_fused_f32(const DevBeam* d_beams, int nbeams, int64_t total_ti
     RFIM_FF(32, 2)
     RFIM_FF(64, 1)
 #undef RFIM_FF
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_td_two_f32(const DevBeam* d_all, const unsigned* tiny_n, const int2* tiny_items, int grid,
+                             const Segment& seg, float4* rec, unsigned* wide_n, int2* wide_items,
+                             unsigned long long* counts, int count_stride, hipStream_t s) {
+    if (grid <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_td_two_f32, dim3(grid), dim3(1024), 0, s, d_all, seg, rec, tiny_n, tiny_items, wide_n,
+                       wide_items, counts, count_stride);
+    return hipGetLastError();
+}
+
+hipError_t launch_fd_two_f32(const DevBeam* d_all, const unsigned* tiny_n, const int2* tiny_items, int grid, int B,
+                             int bpl, const Segment& seg, unsigned* wide_n, int2* wide_items,
+                             unsigned long long* counts, int count_stride, hipStream_t s) {
+    if (grid <= 0) return hipSuccess;
+#define RFIM_F2(B_, BPL_)                                                                            \
+    if (B == B_ && bpl == BPL_) {                                                                    \
+        hipLaunchKernelGGL((k_fd_two_f32<B_, BPL_>), dim3(grid), dim3(kF32Block), 0, s, d_all, seg, tiny_n, \
+                           tiny_items, wide_n, wide_items, counts, count_stride);                    \
+        return hipGetLastError();                                                                    \
+    }
+    RFIM_F2(8, 1)
+    RFIM_F2(8, 2)
+    RFIM_F2(16, 1)
+    RFIM_F2(16, 2)
+    RFIM_F2(32, 1)
+    RFIM_F2(32, 2)
+    RFIM_F2(64, 1)
+#undef RFIM_F2
     return hipErrorInvalidValue;
 }
 

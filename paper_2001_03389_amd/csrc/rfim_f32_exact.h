@@ -203,6 +203,148 @@ __device__ inline u128 zmax_k2(u128 M, u128 R, const KExact& kx, u128 zcap) {
     }
 }
 
+// ---- wider statistics (two windows) ----------------------------------------
+// A row or time sample whose values reach more than 24 exponents below its
+// largest value keeps a second window 24 exponents lower (unit u1 = u / 2^24);
+// combined sums are S = S0 * 2^24 + S1 and Q = Q0 * 2^48 + Q1 in units of u1
+// and u1^2, which need more than 128 bits for Q and D.
+
+__device__ inline U512 u512_add(const U512& a, const U512& b) {
+    U512 r;
+    u128 c = 0;
+#pragma unroll
+    for (int i = 0; i < 8; i++) {
+        c += (u128)a.w[i] + b.w[i];
+        r.w[i] = (uint64_t)c;
+        c >>= 64;
+    }
+    return r;
+}
+
+// a - b for a >= b
+__device__ inline U512 u512_sub(const U512& a, const U512& b) {
+    U512 r;
+    uint64_t br = 0;
+#pragma unroll
+    for (int i = 0; i < 8; i++) {
+        const uint64_t x = a.w[i], y = b.w[i];
+        const uint64_t d = x - y - br;
+        br = (x < y || (x == y && br)) ? 1 : 0;
+        r.w[i] = d;
+    }
+    return r;
+}
+
+// a * m, truncated to 512 bits (callers keep the product below 2^512)
+__device__ inline U512 u512_mul_u128(const U512& a, u128 m) {
+    const uint64_t m0 = (uint64_t)m, m1 = (uint64_t)(m >> 64);
+    U512 r = u512_from(0);
+#pragma unroll
+    for (int i = 0; i < 8; i++) {
+        const u128 p0 = (u128)a.w[i] * m0;
+        u128 acc = (u128)r.w[i] + (uint64_t)p0;
+        r.w[i] = (uint64_t)acc;
+        if (i + 1 < 8) {
+            const u128 p1 = (u128)a.w[i] * m1;
+            acc = (acc >> 64) + (u128)r.w[i + 1] + (uint64_t)(p0 >> 64) + (uint64_t)p1;
+            r.w[i + 1] = (uint64_t)acc;
+            if (i + 2 < 8) {
+                acc = (acc >> 64) + (u128)r.w[i + 2] + (uint64_t)(p1 >> 64);
+                r.w[i + 2] = (uint64_t)acc;
+                if (i + 3 < 8) r.w[i + 3] += (uint64_t)(acc >> 64);
+            }
+        }
+    }
+    return r;
+}
+
+__device__ inline double u512_to_double(const U512& a) {
+    double v = 0.0;
+#pragma unroll
+    for (int i = 7; i >= 0; i--) v = v * 0x1p64 + (double)a.w[i];
+    return v;
+}
+
+// Q0 * 2^48 + Q1 (Q0, Q1 below 2^128)
+__device__ inline U512 q_combine(u128 Q0, u128 Q1) {
+    U512 a = u512_shl(u512_from(Q0), 48);
+    return u512_add(a, u512_from(Q1));
+}
+
+// n * Q - S^2 (>= 0 by Cauchy-Schwarz) for the combined window sums
+__device__ inline U512 d_combine(uint64_t n, const U512& Q, i128 S) {
+    const u128 Sa = S < 0 ? (u128)(-S) : (u128)S;
+    return u512_sub(u512_mul_u128(Q, (u128)n), u512_mul128(Sa, Sa));
+}
+
+// Largest z in [0, zcap] with M * z^2 <= k^2 * R (R below 2^330, M below 2^32,
+// zcap below 2^100).
+__device__ inline u128 zmax_k2w(u128 M, const U512& R, const KExact& kx, u128 zcap) {
+    if (kx.mode == 2) return zcap;
+    if (kx.k == 0.0) return 0;
+    const u128 mk2 = ((u128)kx.mk2_hi << 64) | kx.mk2_lo;
+    U512 rhs = u512_mul_u128(R, mk2);
+    int lsh = 0;
+    if (kx.ek >= 0) rhs = u512_shl(rhs, 2 * kx.ek);
+    else lsh = -2 * kx.ek;
+    int rb = 0;   // bit length of k^2 R (scaled)
+    for (int i = 7; i >= 0; i--)
+        if (rhs.w[i]) {
+            rb = 64 * i + 64 - __clzll((long long)rhs.w[i]);
+            break;
+        }
+    auto ok = [&](u128 z) -> bool {
+        if (z == 0) return true;
+        // bit lengths settle most comparisons (and keep the exact one in range)
+        const int lo_bits = (bitlen_u128(M) - 1) + 2 * (bitlen_u128(z) - 1) + lsh;   // lhs >= 2^lo_bits
+        const int hi_bits = bitlen_u128(M) + 2 * bitlen_u128(z) + lsh;               // lhs < 2^hi_bits
+        if (lo_bits >= rb) return false;
+        if (hi_bits <= rb - 1) return true;
+        return mz2_le_k2r(M, z, rhs, lsh);
+    };
+    const double est = kx.k * sqrt(u512_to_double(R) / (double)M);
+    u128 z;
+    if (!(est < (double)zcap)) {
+        z = zcap;
+    } else {
+        const double fl = floor(est);
+        const uint64_t hi = (uint64_t)ldexp(fl, -64);
+        const uint64_t lo = (uint64_t)(fl - ldexp((double)hi, 64));
+        z = ((u128)hi << 64) | lo;
+    }
+    if (ok(z)) {
+        u128 step = 1;
+        while (z < zcap) {
+            const u128 nz = zcap - z < step ? zcap : z + step;
+            if (!ok(nz)) {
+                u128 lo = z, hi = nz;
+                while (hi - lo > 1) {
+                    const u128 mid = lo + (hi - lo) / 2;
+                    if (ok(mid)) lo = mid; else hi = mid;
+                }
+                return lo;
+            }
+            z = nz;
+            step <<= 1;
+        }
+        return z;
+    }
+    u128 step = 1, hi = z;
+    while (true) {
+        const u128 nz = hi < step ? 0 : hi - step;
+        if (nz == 0 || ok(nz)) {
+            u128 lo = nz;
+            while (hi - lo > 1) {
+                const u128 mid = lo + (hi - lo) / 2;
+                if (ok(mid)) lo = mid; else hi = mid;
+            }
+            return lo;
+        }
+        hi = nz;
+        step <<= 1;
+    }
+}
+
 // Split of an exact square d = a^2 < 2^96 (an integer held in FP64) into a
 // multiple of 2^48 and a remainder of magnitude at most 2^47.
 __device__ inline void split_sq(double d, double* hi, double* lo) {

@@ -73,11 +73,20 @@ hipError_t launch_zero_u64(unsigned long long* p, int64_t n, hipStream_t s);
 // counter.  nt x vpt: work-group size and values per lane of the TD kernel
 // (nt * vpt >= T).  B, bpl: fast FD bin size (0 = none) and bins per lane.
 hipError_t launch_td_rows_f32(const DevBeam* d_beams, int nbeams, int64_t total_rows, int nt, int vpt,
-                              const Segment& seg, float4* rec, unsigned* wide_n, int2* wide_items,
-                              unsigned long long* counts, int count_stride, hipStream_t s);
+                              const Segment& seg, float4* rec, unsigned* tiny_n, int2* tiny_items, unsigned* wide_n,
+                              int2* wide_items, unsigned long long* counts, int count_stride, hipStream_t s);
+hipError_t launch_td_two_f32(const DevBeam* d_all, const unsigned* tiny_n, const int2* tiny_items, int grid,
+                             const Segment& seg, float4* rec, unsigned* wide_n, int2* wide_items,
+                             unsigned long long* counts, int count_stride, hipStream_t s);
 hipError_t launch_fused_f32(const DevBeam* d_beams, int nbeams, int64_t total_tiles, int B, int bpl,
-                            const Segment& seg, const float4* rec, size_t lds_bytes, unsigned* wide_n,
-                            int2* wide_items, unsigned long long* counts, int count_stride, hipStream_t s);
+                            const Segment& seg, const float4* rec, size_t lds_bytes, unsigned* tiny_n,
+                            int2* tiny_items, unsigned* wide_n, int2* wide_items, unsigned long long* counts,
+                            int count_stride, hipStream_t s);
+// time samples listed by the fused kernel for both windows; the all-beam
+// table carries each beam's fast bin shape in Tt (B) and Cp (bins per lane)
+hipError_t launch_fd_two_f32(const DevBeam* d_all, const unsigned* tiny_n, const int2* tiny_items, int grid, int B,
+                             int bpl, const Segment& seg, unsigned* wide_n, int2* wide_items,
+                             unsigned long long* counts, int count_stride, hipStream_t s);
 hipError_t launch_td_wide_f32(const DevBeam* d_all, const unsigned* wide_n, const int2* items, int grid,
                               const Segment& seg, float4* rec, unsigned long long* counts, int count_stride,
                               hipStream_t s);

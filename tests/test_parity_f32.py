@@ -249,3 +249,35 @@ def test_mixed_dtype_batch_matches_single_calls(rf):
         np.testing.assert_array_equal(out[i].view(np.uint8), o1[0].view(np.uint8), err_msg=f"beam {i}")
         np.testing.assert_array_equal(fl[i], f1[0], err_msg=f"beam {i} flags")
     check_against_oracle([beams[1], beams[3]], steps, [out[1], out[3]], [fl[1], fl[3]])
+
+
+@pytest.mark.parametrize("case", ["td-tiny", "fd-tiny", "both-tiny", "tiny-and-wide", "tiny-mean-rows",
+                                  "long-rows-tiny"])
+def test_second_window_paths_f32(rf, case):
+    """Rows and time samples with a few values 2^24..2^48 below their largest
+    (the two-window kernels), mixed with values further down (wide kernels)."""
+    rng = np.random.default_rng(77)
+    C, T = 128, 2000
+    x = rng.standard_normal((C, T))
+    if case in ("td-tiny", "both-tiny", "tiny-and-wide"):
+        m = rng.random((C, T)) < 0.002
+        x[m] *= 2.0 ** -30
+    if case in ("fd-tiny", "both-tiny"):
+        cols = rng.choice(T, 40, replace=False)
+        x[rng.integers(0, C, 40), cols] *= 2.0 ** -35
+    if case == "tiny-and-wide":
+        x[rng.random((C, T)) < 0.0005] *= 2.0 ** -70
+    if case == "tiny-mean-rows":
+        x *= 1e-6
+        x[:, 0] = 8.0
+        x[:, 1] = -8.0
+    if case == "long-rows-tiny":
+        C, T = 32, 40000
+        x = rng.standard_normal((C, T))
+        x[rng.random((C, T)) < 0.0005] *= 2.0 ** -33
+    x = x.astype(np.float32)
+    for steps in ([synth.td(3.25), synth.td(3.0, "median"), synth.fd(2.75, 32), synth.fd(2.5, 32, "median")],
+                  [synth.td(2.5, "median"), synth.fd(2.25, 16), synth.fd(2.0, 16, "median")]):
+        say(f"second window {case} {x.shape} steps={steps}")
+        out, fl, counts = gpu_run(rf, [x], steps, plan=True)
+        check_against_oracle([x], steps, out, fl, counts=counts)
