@@ -246,6 +246,12 @@ __device__ inline void td_row_f32(const DevBeam& bm, int64_t c, const Segment& s
     const int e = EM - 174, e2 = EM - 198;
     const uint32_t n = (uint32_t)T;
 
+    // The row's lower median m stays the lower median after a step that replaces
+    // its cut samples by m while keeping m itself (cut samples lie strictly below
+    // Lo <= m or above H >= m, and the counts on either side of m then keep m at
+    // rank floor((n-1)/2)); known_med says m is current.
+    bool known_med = false;
+    float cur_med = 0.0f;
     for (int j = 0; j < seg.n_td && !bad && !to_two; j++) {
         const SegStep& st = seg.td[j];
         // exact window sums (both windows when the row has values below the first)
@@ -290,8 +296,8 @@ __device__ inline void td_row_f32(const DevBeam& bm, int64_t c, const Segment& s
             s_Q1[wave][1] = (uint64_t)(Q1 >> 64);
         }
         __syncthreads();
-        float med = 0.0f;
-        if (st.replace == RFIM_REPLACE_MEDIAN) {
+        float med = cur_med;
+        if (st.replace == RFIM_REPLACE_MEDIAN && !known_med) {
             const uint32_t key = wg_select_key<NT>((uint64_t)(n - 1) / 2, s_hist, s_tot, s_sel, [&](auto&& add) {
 #pragma unroll
                 for (int i = 0; i < VPT; i++)
@@ -343,6 +349,8 @@ __device__ inline void td_row_f32(const DevBeam& bm, int64_t c, const Segment& s
         const float Lo = s_dec[0], H = s_dec[1], r = s_dec[2];
         bad = s_bad == 1;
         to_two = s_bad == 2;   // a replacement below the first window joins the data
+        known_med = st.replace == RFIM_REPLACE_MEDIAN && !(med < Lo) && !(med > H);
+        cur_med = med;
         uint32_t cnt = 0;
 #pragma unroll
         for (int i = 0; i < VPT; i++) {
