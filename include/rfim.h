@@ -146,14 +146,15 @@ rfim_status rfim_plan_replay_on(rfim_plan* plan, const rfim_beam* beams, int32_t
 rfim_status rfim_autotune(const rfim_beam* shapes, int32_t nbeams, const rfim_step* steps, int32_t nsteps,
                           const char* tune_cache_path, void* stream, double* best_ms);
 
-/* Tuning-cache access without a GPU: rfim_tune_lookup fills out3 =
- * {uint8 tile cap, float32 LDS bytes, float32 tile cap} for the key of these
- * shapes and steps (RFIM_ERR_UNSUPPORTED: no entry or no file);
- * rfim_tune_store adds or replaces that entry. */
+/* Tuning-cache access without a GPU: rfim_tune_lookup fills out4 =
+ * {uint8 tile cap (samples), float32 LDS budget (bytes), float32 tile cap,
+ * uint8 LDS budget (bytes)} for the key of these shapes and steps
+ * (RFIM_ERR_UNSUPPORTED: no entry or no file); rfim_tune_store adds or
+ * replaces that entry (RFIM_ERR_INVALID_ARG for values out of range). */
 rfim_status rfim_tune_lookup(const char* path, const rfim_beam* shapes, int32_t nbeams, const rfim_step* steps,
-                             int32_t nsteps, int64_t* out3);
+                             int32_t nsteps, int64_t* out4);
 rfim_status rfim_tune_store(const char* path, const rfim_beam* shapes, int32_t nbeams, const rfim_step* steps,
-                            int32_t nsteps, const int64_t* params3, double ms);
+                            int32_t nsteps, const int64_t* params4, double ms);
 
 /* Per (beam, step) number of replaced samples of the most recent run with
  * this plan, copied to host_out[nbeams * nsteps]; synchronises the plan's

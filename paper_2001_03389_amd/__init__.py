@@ -218,20 +218,24 @@ def _shape_array(shapes):
 
 
 def tune_lookup(path: str, shapes: Sequence[rfim_beam], steps: Sequence):
-    """(uint8 tile cap, float32 LDS bytes, float32 tile cap) stored in the
-    tuning cache for these shapes and steps, or None (rfim_tune_lookup)."""
-    out = (ctypes.c_int64 * 3)()
+    """(uint8 tile cap, float32 LDS bytes, float32 tile cap, uint8 LDS bytes)
+    stored in the tuning cache for these shapes and steps, or None
+    (rfim_tune_lookup)."""
+    out = (ctypes.c_int64 * 4)()
     rc = lib().rfim_tune_lookup(path.encode(), _shape_array(shapes), len(shapes), make_steps(steps),
                                 len(steps), out)
     if rc == RFIM_ERR_UNSUPPORTED:
         return None
     _check(rc, "rfim_tune_lookup")
-    return int(out[0]), int(out[1]), int(out[2])
+    return tuple(int(v) for v in out)
 
 
 def tune_store(path: str, shapes: Sequence[rfim_beam], steps: Sequence, params, ms: float = 0.0) -> None:
     """Adds or replaces the cache entry of these shapes and steps (rfim_tune_store)."""
-    p = (ctypes.c_int64 * 3)(*[int(v) for v in params])
+    vals = [int(v) for v in params]
+    if len(vals) == 3:
+        vals.append(51200)   # default uint8 LDS budget
+    p = (ctypes.c_int64 * 4)(*vals)
     _check(lib().rfim_tune_store(path.encode(), _shape_array(shapes), len(shapes), make_steps(steps),
                                  len(steps), p, float(ms)), "rfim_tune_store")
 

@@ -65,10 +65,9 @@ size_t elem_size(int32_t dt) { return dt == RFIM_U8 ? 1 : 4; }
 namespace {
 
 constexpr int kRing = 64;   // table staging slots per workspace
-// uint8 fused-kernel tile LDS per work-group: 160 KB per CU shared by three
-// work-groups, less the kernel's static LDS (TD exception worklist, counters)
-constexpr size_t kLdsBudget = 51200;
-constexpr size_t kLdsMax = 65536;
+// largest uint8 fused-kernel tile (bytes of LDS); the default budget (tuning
+// parameter) leaves three work-groups per CU
+constexpr size_t kLdsMax = 131072;
 
 bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
     uintptr_t x = (uintptr_t)a, y = (uintptr_t)b;
@@ -107,24 +106,6 @@ std::vector<Segment> segments_of(const rfim_step* steps, int32_t nsteps) {
     return out;
 }
 
-// uint8 fused-kernel tile for one beam: Tt samples (power of two in [4, cap])
-// and Cp LDS bytes per time sample
-bool tile_shape_u8(const rfim_beam& b, bool flags, int cap, int32_t* Tt, int32_t* Cp) {
-    if (b.nchan >= ((int64_t)1 << 24)) return false;   // worklist packs the row in 24 bits
-    // 16-byte aligned time samples (vector LDS reads), padded off a multiple
-    // of 256 bytes so the transposed stores of neighbouring lanes spread over banks
-    int64_t cp = ((b.nchan + 15) / 16) * 16;
-    if (cp % 256 == 0 || cp % 256 == 128) cp += 16;
-    size_t per = (size_t)cp * (flags ? 2 : 1);
-    int t = 4;
-    while (t * 2 <= cap && t < 64) t *= 2;
-    while (t > 4 && per * t > kLdsBudget) t >>= 1;
-    if (per * t > kLdsMax) return false;
-    *Tt = t;
-    *Cp = (int32_t)cp;
-    return true;
-}
-
 // LDS a work-group may use (the device limit, queried once)
 size_t lds_limit() {
     static size_t lim = [] {
@@ -135,6 +116,24 @@ size_t lds_limit() {
         return (size_t)v;
     }();
     return lim;
+}
+
+// uint8 fused-kernel tile for one beam: Tt samples (power of two in [4, cap])
+// and Cp LDS bytes per time sample
+bool tile_shape_u8(const rfim_beam& b, bool flags, int cap, size_t budget, int32_t* Tt, int32_t* Cp) {
+    if (b.nchan >= ((int64_t)1 << 24)) return false;   // worklist packs the row in 24 bits
+    // 16-byte aligned time samples (vector LDS reads), padded off a multiple
+    // of 256 bytes so the transposed stores of neighbouring lanes spread over banks
+    int64_t cp = ((b.nchan + 15) / 16) * 16;
+    if (cp % 256 == 0 || cp % 256 == 128) cp += 16;
+    size_t per = (size_t)cp * (flags ? 2 : 1);
+    int t = 4;
+    while (t * 2 <= cap && t < 64) t *= 2;
+    while (t > 4 && per * t > budget) t >>= 1;
+    if (per * t > std::min(kLdsMax, lds_limit() - 4096)) return false;
+    *Tt = t;
+    *Cp = (int32_t)cp;
+    return true;
 }
 
 struct Slot {
@@ -441,7 +440,7 @@ rfim_status make_launch_plan(const rfim_beam* beams, int32_t nbeams, const rfim_
             continue;
         }
         lp->u8_beams.push_back(i);
-        if (!tile_shape_u8(b, b.flags != nullptr, tune.u8_tile_cap, &lp->Tt[i], &lp->Cp[i]))
+        if (!tile_shape_u8(b, b.flags != nullptr, tune.u8_tile_cap, tune.u8_lds, &lp->Tt[i], &lp->Cp[i]))
             return RFIM_ERR_UNSUPPORTED;
         lp->u8_rows += b.nchan;
         lp->u8_tiles += (b.nsamp + lp->Tt[i] - 1) / lp->Tt[i];

@@ -14,6 +14,7 @@ struct TuneParams {
     int u8_tile_cap = 64;        // largest uint8 fused-kernel tile (samples, power of two)
     size_t f32_lds = 81920;      // LDS budget of a float32 fused work-group (bytes)
     int f32_tile_cap = 64;       // largest float32 fused-kernel tile (samples)
+    size_t u8_lds = 51200;       // LDS budget of a uint8 fused work-group (bytes)
 };
 
 // Defaults; RFIM_TILE_T, RFIM_F32_LDS and RFIM_F32_TILE_T in the environment

@@ -11,7 +11,8 @@
 // the beam shapes and the step list; rfim_plan_create reads it back.
 //
 // Cache file: one JSON object; each entry sits on its own line,
-//   "<key>": {"u8_tile_cap": 64, "f32_lds": 81920, "f32_tile_cap": 64, "ms": 1.5, "candidates": 9}
+//   "<key>": {"u8_tile_cap": 64, "f32_lds": 81920, "f32_tile_cap": 64, "u8_lds": 51200, "ms": 1.5,
+//             "candidates": 9}
 #include <algorithm>
 #include <cstdio>
 #include <cstdlib>
@@ -38,6 +39,10 @@ TuneParams default_tune() {
     if (const char* e = std::getenv("RFIM_F32_TILE_T")) {
         const int v = std::atoi(e);
         if (v >= 4) p.f32_tile_cap = v;
+    }
+    if (const char* e = std::getenv("RFIM_U8_LDS")) {
+        const long v = std::atol(e);
+        if (v >= 4096) p.u8_lds = (size_t)v;
     }
     return p;
 }
@@ -95,13 +100,16 @@ rfim_status tune_cache_lookup(const char* path, const rfim_beam* shapes, int32_t
     const std::string pre = entry_prefix(tune_key(shapes, nbeams, steps, nsteps));
     for (const std::string& l : lines) {
         if (l.compare(0, pre.size(), pre) != 0) continue;
-        double a = 0, b = 0, c = 0;
+        double a = 0, b = 0, c = 0, d = 51200;
         if (!field(l, "u8_tile_cap", &a) || !field(l, "f32_lds", &b) || !field(l, "f32_tile_cap", &c))
             return RFIM_ERR_INVALID_ARG;
-        if (a < 4 || a > 64 || b < 1024 || b > (1 << 20) || c < 4 || c > 64) return RFIM_ERR_INVALID_ARG;
+        (void)field(l, "u8_lds", &d);   // optional, default budget
+        if (a < 4 || a > 64 || b < 1024 || b > (1 << 20) || c < 4 || c > 64 || d < 4096 || d > (1 << 20))
+            return RFIM_ERR_INVALID_ARG;
         out->u8_tile_cap = (int)a;
         out->f32_lds = (size_t)b;
         out->f32_tile_cap = (int)c;
+        out->u8_lds = (size_t)d;
         return RFIM_OK;
     }
     return RFIM_ERR_UNSUPPORTED;
@@ -123,8 +131,9 @@ rfim_status tune_cache_store(const char* path, const rfim_beam* shapes, int32_t 
     }
     char buf[256];
     std::snprintf(buf, sizeof buf,
-                  "\"u8_tile_cap\": %d, \"f32_lds\": %zu, \"f32_tile_cap\": %d, \"ms\": %.6f, \"candidates\": %d}",
-                  p.u8_tile_cap, p.f32_lds, p.f32_tile_cap, ms, candidates);
+                  "\"u8_tile_cap\": %d, \"f32_lds\": %zu, \"f32_tile_cap\": %d, \"u8_lds\": %zu, \"ms\": %.6f, "
+                  "\"candidates\": %d}",
+                  p.u8_tile_cap, p.f32_lds, p.f32_tile_cap, p.u8_lds, ms, candidates);
     entries.push_back(pre + buf);
     const std::string tmp = std::string(path) + ".tmp";
     {
@@ -209,26 +218,28 @@ using namespace rfim;
 extern "C" {
 
 rfim_status rfim_tune_lookup(const char* path, const rfim_beam* shapes, int32_t nbeams, const rfim_step* steps,
-                             int32_t nsteps, int64_t* out3) {
-    if (!path || !shapes || nbeams < 1 || !steps || nsteps < 1 || !out3) return RFIM_ERR_INVALID_ARG;
+                             int32_t nsteps, int64_t* out4) {
+    if (!path || !shapes || nbeams < 1 || !steps || nsteps < 1 || !out4) return RFIM_ERR_INVALID_ARG;
     TuneParams p;
     const rfim_status st = tune_cache_lookup(path, shapes, nbeams, steps, nsteps, &p);
     if (st != RFIM_OK) return st;
-    out3[0] = p.u8_tile_cap;
-    out3[1] = (int64_t)p.f32_lds;
-    out3[2] = p.f32_tile_cap;
+    out4[0] = p.u8_tile_cap;
+    out4[1] = (int64_t)p.f32_lds;
+    out4[2] = p.f32_tile_cap;
+    out4[3] = (int64_t)p.u8_lds;
     return RFIM_OK;
 }
 
 rfim_status rfim_tune_store(const char* path, const rfim_beam* shapes, int32_t nbeams, const rfim_step* steps,
-                            int32_t nsteps, const int64_t* params3, double ms) {
-    if (!path || !shapes || nbeams < 1 || !steps || nsteps < 1 || !params3) return RFIM_ERR_INVALID_ARG;
+                            int32_t nsteps, const int64_t* params4, double ms) {
+    if (!path || !shapes || nbeams < 1 || !steps || nsteps < 1 || !params4) return RFIM_ERR_INVALID_ARG;
     TuneParams p;
-    p.u8_tile_cap = (int)params3[0];
-    p.f32_lds = (size_t)params3[1];
-    p.f32_tile_cap = (int)params3[2];
+    p.u8_tile_cap = (int)params4[0];
+    p.f32_lds = (size_t)params4[1];
+    p.f32_tile_cap = (int)params4[2];
+    p.u8_lds = (size_t)params4[3];
     if (p.u8_tile_cap < 4 || p.u8_tile_cap > 64 || p.f32_lds < 1024 || p.f32_lds > (1u << 20) ||
-        p.f32_tile_cap < 4 || p.f32_tile_cap > 64)
+        p.f32_tile_cap < 4 || p.f32_tile_cap > 64 || p.u8_lds < 4096 || p.u8_lds > (1u << 20))
         return RFIM_ERR_INVALID_ARG;
     return tune_cache_store(path, shapes, nbeams, steps, nsteps, p, ms, 0);
 }
@@ -285,21 +296,25 @@ rfim_status rfim_autotune(const rfim_beam* shapes, int32_t nbeams, const rfim_st
     const TuneParams def = default_tune();
     cands.push_back(def);
     const int u8caps[] = {16, 32, 64};
+    const size_t u8lds[] = {51200, 102400};
     const size_t f32lds[] = {40960, 81920, 163840};
     const int f32caps[] = {8, 64};
     for (int a : u8caps)
-        for (size_t l : f32lds)
-            for (int c : f32caps) {
-                if (!any_u8 && a != def.u8_tile_cap) continue;
-                if (!any_f32 && (l != def.f32_lds || c != def.f32_tile_cap)) continue;
-                TuneParams p;
-                p.u8_tile_cap = a;
-                p.f32_lds = l;
-                p.f32_tile_cap = c;
-                if (p.u8_tile_cap == def.u8_tile_cap && p.f32_lds == def.f32_lds && p.f32_tile_cap == def.f32_tile_cap)
-                    continue;
-                cands.push_back(p);
-            }
+        for (size_t ul : u8lds)
+            for (size_t l : f32lds)
+                for (int c : f32caps) {
+                    if (!any_u8 && (a != def.u8_tile_cap || ul != def.u8_lds)) continue;
+                    if (!any_f32 && (l != def.f32_lds || c != def.f32_tile_cap)) continue;
+                    TuneParams p;
+                    p.u8_tile_cap = a;
+                    p.u8_lds = ul;
+                    p.f32_lds = l;
+                    p.f32_tile_cap = c;
+                    if (p.u8_tile_cap == def.u8_tile_cap && p.u8_lds == def.u8_lds && p.f32_lds == def.f32_lds &&
+                        p.f32_tile_cap == def.f32_tile_cap)
+                        continue;
+                    cands.push_back(p);
+                }
 
     hipEvent_t e0 = nullptr, e1 = nullptr;
     (void)hipEventCreate(&e0);

@@ -292,9 +292,11 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) voi
         }
     };
 
-    // A two-pass form (exact S1, S2 by dot4, then a histogram of the samples
-    // outside the middle of the first cut only) costs a second read of the row
-    // from L2/MALL, which measures slower than one pass with a full histogram.
+    // Measured alternatives, both slower than one pass with a full histogram:
+    // exact S1, S2 by dot4 with a histogram of only the bytes outside a band
+    // around the row's bulk (in one pass with a band from the row's first 2 KB,
+    // or in two passes with the band from the first cut): in nearly every
+    // wave-wide dword some lane still holds an out-of-band byte.
     bool done = false;
     (void)median;
     if (!done) {

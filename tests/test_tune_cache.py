@@ -29,10 +29,10 @@ def test_round_trip_replace_and_json(tmp_path):
     rf.tune_store(p, shapes_a(), STEPS, (32, 81920, 64), 1.25)
     other = [rf.shape_beam("u8", 384, 25000, flags=True)]
     rf.tune_store(p, other, STEPS, (16, 40960, 8), 0.5)
-    assert rf.tune_lookup(p, shapes_a(), STEPS) == (32, 81920, 64)
-    assert rf.tune_lookup(p, other, STEPS) == (16, 40960, 8)
-    rf.tune_store(p, shapes_a(), STEPS, (64, 163840, 8), 1.0)    # replaces
-    assert rf.tune_lookup(p, shapes_a(), STEPS) == (64, 163840, 8)
+    assert rf.tune_lookup(p, shapes_a(), STEPS) == (32, 81920, 64, 51200)
+    assert rf.tune_lookup(p, other, STEPS) == (16, 40960, 8, 51200)
+    rf.tune_store(p, shapes_a(), STEPS, (64, 163840, 8, 102400), 1.0)    # replaces
+    assert rf.tune_lookup(p, shapes_a(), STEPS) == (64, 163840, 8, 102400)
     doc = json.load(open(p))
     assert len(doc) == 2
     assert all(set(v) >= {"u8_tile_cap", "f32_lds", "f32_tile_cap", "ms"} for v in doc.values())
@@ -70,6 +70,6 @@ def test_malformed_entry_rejected(tmp_path):
 
 def test_store_rejects_out_of_range(tmp_path):
     p = str(tmp_path / "tune.json")
-    for bad in [(2, 81920, 64), (32, 10, 64), (32, 81920, 128)]:
+    for bad in [(2, 81920, 64), (32, 10, 64), (32, 81920, 128), (32, 81920, 64, 100)]:
         with pytest.raises(rf.RfimError):
             rf.tune_store(p, shapes_a(), STEPS, bad, 1.0)
