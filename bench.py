@@ -68,7 +68,7 @@ def read_traffic(kernel: str, workload: str):
     return int(float(kv["traffic_bytes_per_launch"]))
 
 
-def summarize(stats_csv, fetch_csv, write_csv, command, workload):
+def summarize(stats_csv, fetch_csv, write_csv, command, workload, copy_bytes):
     """Writes profiles/ summaries from rocprofv3 CSV output (kernel stats, and
     FETCH_SIZE / WRITE_SIZE counter runs that include one plain device copy of
     the batch size as calibration)."""
@@ -101,7 +101,6 @@ def summarize(stats_csv, fetch_csv, write_csv, command, workload):
 
     fetch, fcopy = per_kernel(fetch_csv, "FETCH_SIZE")
     write, wcopy = per_kernel(write_csv, "WRITE_SIZE")
-    copy_bytes = int(os.environ.get("RFIM_COPY_BYTES", 768000000))
     ff = copy_bytes / (fcopy * 1024.0)
     wf = copy_bytes / (wcopy * 1024.0)
     for k in sorted(set(fetch) & set(write)):
@@ -228,6 +227,28 @@ def serve_sweep(rf, torch, dev, budget_s=45.0):
     return out
 
 
+def workload_of(args):
+    """(beam specs, steps, description, dtype) of the workload named by args."""
+    import synth
+    if args.workload == "arts40":
+        specs = synth.arts40_specs(args.beams)
+        steps = synth.STEPS_ARTS40_MEAN if args.replace == "mean" else synth.STEPS_ARTS40_MEDIAN
+        desc = (f"{len(specs)} beams x 1536 ch x 12500 samples uint8, "
+                f"TD 4.0/3.5/3.25 + FD 3.0/2.75 (32-ch bins), {args.replace} replacement")
+        return specs, steps, desc, "u8"
+    if args.workload == "uneven72":
+        specs = synth.uneven72_specs()
+        desc = ("72 beams in one call: 64 uint8 (16 each of 1536x12500, 384x25000, 4096x8192, 768x16384) + "
+                "8 float32 (2 per shape), TD 3.25 + FD 2.75 (32-ch bins), mean; "
+                + ("default tuning" if args.no_autotune else "autotuned plan") + ", HIP-graph replay")
+        return specs, synth.STEPS_ARTS1, desc, "u8+f32"
+    specs = synth.stress16_specs()
+    desc = ("16 beams x 4096 ch x 65536 samples float32 (5% RFI channels, bursty impulses), "
+            "TD 4.0/3.5/3.25/3.25 + FD 3.0/2.75/2.75 (32-ch bins), median, "
+            + ("in-place" if args.inplace else "out-of-place"))
+    return specs, synth.STEPS_STRESS, desc, "f32"
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -239,6 +260,8 @@ def main():
     ap.add_argument("--inplace", action="store_true", help="stress16: in-place run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serve", action="store_true", help="skip the real-time serve sweep")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="uneven72: default tuning parameters instead of an autotuned plan")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain device copy of the batch size (for counter scaling)")
     ap.add_argument("--summarize", nargs=3, metavar=("STATS_CSV", "FETCH_CSV", "WRITE_CSV"),
@@ -248,7 +271,9 @@ def main():
     wl_name = {"arts40": f"arts40_{args.replace}", "uneven72": "uneven72",
                "stress16": "stress16_" + ("inplace" if args.inplace else "outofplace")}[args.workload]
     if args.summarize:
-        summarize(*args.summarize, args.profile_command, wl_name)
+        specs = workload_of(args)[0]
+        summarize(*args.summarize, args.profile_command, wl_name,
+                  sum(sp.nchan * sp.nsamp * (1 if sp.dtype == "u8" else 4) for sp in specs))
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for {args.gpus}); beams are independent, "
@@ -267,25 +292,7 @@ def main():
     # a stream of our own: a HIP graph cannot be captured on the null stream
     stream = torch.cuda.Stream() if args.workload == "uneven72" else torch.cuda.current_stream()
 
-    if args.workload == "arts40":
-        specs = synth.arts40_specs(args.beams)
-        steps = synth.STEPS_ARTS40_MEAN if args.replace == "mean" else synth.STEPS_ARTS40_MEDIAN
-        desc = (f"{len(specs)} beams x 1536 ch x 12500 samples uint8, "
-                f"TD 4.0/3.5/3.25 + FD 3.0/2.75 (32-ch bins), {args.replace} replacement")
-        dtype = "u8"
-    elif args.workload == "uneven72":
-        specs = synth.uneven72_specs()
-        steps = synth.STEPS_ARTS1
-        desc = ("72 beams in one call: 64 uint8 (16 each of 1536x12500, 384x25000, 4096x8192, 768x16384) + "
-                "8 float32 (2 per shape), TD 3.25 + FD 2.75 (32-ch bins), mean; autotuned plan, HIP-graph replay")
-        dtype = "u8+f32"
-    else:
-        specs = synth.stress16_specs()
-        steps = synth.STEPS_STRESS
-        desc = ("16 beams x 4096 ch x 65536 samples float32 (5% RFI channels, bursty impulses), "
-                "TD 4.0/3.5/3.25/3.25 + FD 3.0/2.75/2.75 (32-ch bins), median, "
-                + ("in-place" if args.inplace else "out-of-place"))
-        dtype = "f32"
+    specs, steps, desc, dtype = workload_of(args)
     log(f"generating and uploading {len(specs)} beams ...")
     t = time.time()
     ins, host = [], []
@@ -304,7 +311,7 @@ def main():
 
     tune_info = None
     cache = None
-    if args.workload == "uneven72":
+    if args.workload == "uneven72" and not args.no_autotune:
         import tempfile
         cache = os.path.join(tempfile.mkdtemp(), "rfim_tune.json")
         shapes = [rf.shape_beam(dt, c, t_) for c, t_, dt in shapes_all]
