@@ -5,6 +5,32 @@
 
 namespace rfim {
 
+// Loads and stores through global-address-space pointers.  Beam pointers come
+// from launch tables in memory, so the compiler would otherwise address them
+// as flat, which may alias LDS and forces waits on LDS traffic around them.
+// (uint4 goes through a native vector type: copying HIP's uint4 struct takes a
+// generic reference and would turn the access back into a flat one.)
+typedef unsigned int rfim_u32x4 __attribute__((ext_vector_type(4)));
+template <typename T>
+__device__ inline T ld_global(const void* p) {
+    return *(const __attribute__((address_space(1))) T*)p;
+}
+template <>
+__device__ inline uint4 ld_global<uint4>(const void* p) {
+    const rfim_u32x4 v = *(const __attribute__((address_space(1))) rfim_u32x4*)p;
+    return make_uint4(v.x, v.y, v.z, v.w);
+}
+template <typename T>
+__device__ inline void st_global(void* p, const T& v) {
+    *(__attribute__((address_space(1))) T*)p = v;
+}
+template <>
+__device__ inline void st_global<uint4>(void* p, const uint4& v) {
+    rfim_u32x4 w;
+    w.x = v.x; w.y = v.y; w.z = v.z; w.w = v.w;
+    *(__attribute__((address_space(1))) rfim_u32x4*)p = w;
+}
+
 // last beam of a launch table whose first row (tile) is <= g
 __device__ inline int find_beam_by_row(const DevBeam* beams, int nbeams, int64_t g) {
     int lo = 0, hi = nbeams - 1;

@@ -141,24 +141,6 @@ __device__ inline int64_t ceil_div(int64_t a, int64_t b) {  // b > 0
     return q;
 }
 
-// TD test of one uint8 value v in a row with n samples, S1 = sum x and
-// D = n*S2 - S1^2: true when v is NOT an outlier, (n*v - S1)^2 <= k^2 * D.
-// kd2 = k*k and Dd = D, both rounded to double: when the two sides differ by
-// more than the rounding can explain the FP64 comparison decides, otherwise
-// the exact integer test does.
-__device__ inline bool td_keeps_u8(uint64_t n, uint64_t S1, u128 D, double kd2, double Dd, uint32_t v,
-                                   const KExact& kx) {
-    const int64_t d = (int64_t)(n * v) - (int64_t)S1;      // |d| < 2^39: exact in double
-    const double dd = (double)d;
-    const double lhs = dd * dd, rhs = kd2 * Dd;               // each within 3 ulp of exact
-    if (kx.mode == 0) {
-        if (lhs < rhs * (1.0 - 0x1p-48)) return true;
-        if (lhs > rhs * (1.0 + 0x1p-48)) return false;
-    }
-    const u128 a = d < 0 ? (u128)(-d) : (u128)d;
-    return le_k2(a * a, D, kx);
-}
-
 // FD cut of one time sample: the largest z in [0, zcap] with C*z^2 <= k^2 SZ2;
 // channel c is an outlier exactly when |Z_c| > z (Z_c is an integer, |Z_c| <= zcap).
 __device__ inline uint64_t fd_zthr(u128 SZ2, int64_t C, const KExact& kx, uint64_t zcap) {

@@ -17,7 +17,7 @@ struct TuneParams {
     size_t u8_lds = 51200;       // LDS budget of a uint8 fused work-group (bytes)
 };
 
-// Defaults; RFIM_TILE_T, RFIM_F32_LDS and RFIM_F32_TILE_T in the environment
+// Defaults; RFIM_TILE_T, RFIM_F32_LDS, RFIM_F32_TILE_T and RFIM_U8_LDS in the environment
 // override them (experiments).
 TuneParams default_tune();
 

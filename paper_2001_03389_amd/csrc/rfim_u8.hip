@@ -81,7 +81,7 @@ __device__ inline void store4(uint8_t* p, uint32_t v, int64_t t, int64_t T) {
 namespace {
 
 constexpr int kHistCopies = 4;     // per wave, lane & 3 picks the copy
-constexpr int kHistPitch = 272;    // words per copy (copies 16 banks apart)
+constexpr int kHistPitch = 272;    // words per histogram copy (copies 16 banks apart)
 constexpr int kRowsPerWG = kBlock / 64;
 
 // Sum over the 64 lanes with DPP row rotations (every lane of a 16-lane row
@@ -125,7 +125,11 @@ __device__ inline void hist4(uint32_t* h, uint32_t v) {
 }  // namespace
 
 // One pass over a row by one wave: dword-aligned 16-byte loads for the bulk,
-// single bytes for the unaligned head and the tail.
+// single bytes for the unaligned head and the tail.  The bulk goes in chunks
+// of kRowChunk 16-byte loads per lane, all issued before any is consumed, so
+// a wave waits for memory once per chunk (16 KB of row) rather than once per
+// load.
+constexpr int kRowChunk = 16;
 template <typename FD, typename FB>
 __device__ inline void row_pass(const uint8_t* row, int64_t T, int lane, FD&& on_dword, FB&& on_byte) {
     int64_t head = (int64_t)((4 - ((uintptr_t)row & 3)) & 3);
@@ -133,41 +137,32 @@ __device__ inline void row_pass(const uint8_t* row, int64_t T, int lane, FD&& on
     if (lane < head) on_byte((uint32_t)row[lane]);
     const int64_t n16 = (T - head) >> 4;
     const uint8_t* body = row + head;
-    int64_t i = lane;
-    for (; i + 64 < n16; i += 128) {
-        const uint4 v0 = *(const uint4*)(body + 16 * i);
-        const uint4 v1 = *(const uint4*)(body + 16 * (i + 64));
-        on_dword(v0.x); on_dword(v0.y); on_dword(v0.z); on_dword(v0.w);
-        on_dword(v1.x); on_dword(v1.y); on_dword(v1.z); on_dword(v1.w);
-    }
-    for (; i < n16; i += 64) {
-        const uint4 v0 = *(const uint4*)(body + 16 * i);
-        on_dword(v0.x); on_dword(v0.y); on_dword(v0.z); on_dword(v0.w);
+    for (int64_t base = 0; base < n16; base += 64 * kRowChunk) {
+        uint4 v[kRowChunk];
+#pragma unroll
+        for (int u = 0; u < kRowChunk; u++) {
+            const int64_t i = base + lane + 64 * u;
+            v[u] = i < n16 ? ld_global<uint4>(body + 16 * i) : make_uint4(0u, 0u, 0u, 0u);
+        }
+#pragma unroll
+        for (int u = 0; u < kRowChunk; u++) {
+            if (base + lane + 64 * u < n16) {
+                on_dword(v[u].x); on_dword(v[u].y); on_dword(v[u].z); on_dword(v[u].w);
+            }
+        }
     }
     for (int64_t k = head + 16 * n16 + lane; k < T; k += 64) on_byte((uint32_t)row[k]);
 }
 
-// Exact TD test of the byte values 4*lane .. 4*lane+3: bit u of the result is
-// set when value 4*lane+u is kept; *lo, *hi = the kept interval over all 256
-// values (wave-uniform; *lo > *hi when empty).
-__device__ inline uint32_t td_keep_interval(uint64_t n, uint64_t S1, u128 D, const KExact& kx, int lane,
-                                            int* lo, int* hi) {
-    uint32_t bits = 0;
-    int l = 256, h = -1;
-    const double kd2 = kx.k * kx.k, Dd = (double)D;
-#pragma unroll 1
-    for (int u = 0; u < 4; u++) {
-        const bool kp = td_keeps_u8(n, S1, D, kd2, Dd, 4 * lane + u, kx);
-        bits |= (kp ? 1u : 0u) << u;
-        const uint64_t km = __ballot(kp);
-        if (km) {
-            l = min(l, 4 * (__ffsll((unsigned long long)km) - 1) + u);
-            h = max(h, 4 * (63 - __clzll((long long)km)) + u);
-        }
-    }
-    *lo = l;
-    *hi = h;
-    return bits;
+// Kept interval of a TD step over the byte values: v is kept exactly when
+// |n*v - S1| <= z, z being the largest integer with z^2 <= k^2 * D (the exact
+// test of the row's mean and population deviation); *lo > *hi when no value
+// is kept.  Wave-uniform.
+__device__ inline void td_interval(uint64_t n, uint64_t S1, u128 D, const KExact& kx, int* lo, int* hi) {
+    const int64_t z = (int64_t)fd_zthr(D, 1, kx, 255 * n);
+    const int64_t l = ceil_div((int64_t)S1 - z, (int64_t)n), h = floor_div((int64_t)S1 + z, (int64_t)n);
+    *lo = (int)(l < 0 ? 0 : (l > 256 ? 256 : l));
+    *hi = (int)(h > 255 ? 255 : (h < -1 ? -1 : h));
 }
 
 // Runs every TD step of the run for one row (one wave).  The row is described
@@ -213,10 +208,12 @@ __device__ bool td_decide(const Segment& seg, uint64_t n, uint32_t hv[4], uint64
         } else {
             r = (int)rn_div_small(S1, n);
         }
-        // every byte value is tested exactly
         const u128 D = (u128)n * S2 - (u128)S1 * S1;
         int lo, hi;
-        const uint32_t keepbits = td_keep_interval(n, S1, D, st.kx, lane, &lo, &hi);
+        td_interval(n, S1, D, st.kx, &lo, &hi);
+        uint32_t keepbits = 0;
+#pragma unroll
+        for (int u = 0; u < 4; u++) keepbits |= (4 * lane + u >= lo && 4 * lane + u <= hi) ? 1u << u : 0u;
         if (nJ > 0 && (lo > jlo || hi < jhi)) return false;   // an untracked value may be cut
         uint32_t moved32 = 0;
 #pragma unroll
@@ -245,7 +242,7 @@ __device__ bool td_decide(const Segment& seg, uint64_t n, uint32_t hv[4], uint64
     return true;
 }
 
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) void k_td_rows_u8(const DevBeam* __restrict__ beams,
+__global__ __launch_bounds__(kBlock) void k_td_rows_u8(const DevBeam* __restrict__ beams,
                                                        int nbeams, int64_t total_rows, Segment seg,
                                                        uint32_t* __restrict__ rec,
                                                        unsigned long long* __restrict__ counts,
@@ -271,8 +268,6 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) voi
     const uint8_t* row = (const uint8_t*)bm.in + c * bm.stride;
     unsigned long long* cnt_row = counts ? counts + (int64_t)bm.cidx * count_stride : nullptr;
     uint32_t* h = hist + (lane & (kHistCopies - 1)) * kHistPitch;
-    bool median = false;
-    for (int j = 0; j < seg.n_td; j++) median |= seg.td[j].replace == RFIM_REPLACE_MEDIAN;
 
     auto clear_hist = [&] {
         for (int i = lane; i < kHistCopies * kHistPitch; i += 64) hist[i] = 0;
@@ -292,14 +287,14 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) voi
         }
     };
 
-    // Measured alternatives, both slower than one pass with a full histogram:
+    // Measured alternatives, all slower than one pass with a full histogram:
     // exact S1, S2 by dot4 with a histogram of only the bytes outside a band
-    // around the row's bulk (in one pass with a band from the row's first 2 KB,
-    // or in two passes with the band from the first cut): in nearly every
-    // wave-wide dword some lane still holds an out-of-band byte.
-    bool done = false;
-    (void)median;
-    if (!done) {
+    // around the row's bulk (a band from the row's first 2 KB; a band from the
+    // first cut in a second pass; or the row held in VGPRs with the dwords
+    // holding out-of-band bytes compacted into an LDS queue first).  The
+    // first two leave some out-of-band byte in nearly every wave-wide dword;
+    // the last costs more occupancy than the atomics it saves.
+    {
         // every value tracked: the row's full histogram
         clear_hist();
         row_pass(row, T, lane, [&](uint32_t x) { hist4(h, x); }, [&](uint32_t x) { atomicAdd(&h[x], 1u); });
@@ -510,29 +505,37 @@ __device__ inline void tile_load_task(const TileCtx& k, int64_t idx, uint8_t* ti
     }
 }
 
-// Phase 1 body for a 4-row x 16-sample task of an interior tile whose rows
-// are dword aligned: one 16-byte load per row
-__device__ inline void tile_load_task16(const TileCtx& k, int64_t idx, uint8_t* tile, uint8_t* ftile,
-                                        bool want_flags, bool or_flags, uint32_t* exc_pos,
-                                        uint32_t* exc_n) {
+// Phase 1 for a 4-row x 16-sample task of an interior tile whose rows are
+// dword aligned, in two halves so that a thread can issue the loads of all
+// its tasks before it waits for any: fetch16 loads the 4 rows (one 16-byte
+// load each) and their last TD records, load_task16 does the rest.
+__device__ inline void fetch16(const TileCtx& k, int64_t idx, uint4 x[4], uint32_t e[4]) {
     const int tq_log = k.tw_log - 2;              // 16-sample chunks per tile row
     const int64_t q4 = idx >> tq_log;
     const int w16 = (int)(idx & ((1 << tq_log) - 1));
     const int64_t c0 = 4 * q4;
-    uint4 x[4];
 #pragma unroll
     for (int i = 0; i < 4; i++) {
         const int64_t c = c0 + i < k.C ? c0 + i : k.C - 1;
-        x[i] = *(const uint4*)(k.in + c * k.stride + k.t0 + 16 * w16);
+        x[i] = ld_global<uint4>(k.in + c * k.stride + k.t0 + 16 * w16);
+        e[i] = k.n_td > 0 ? ld_global<uint32_t>(k.rec + c * k.n_td + (k.n_td - 1)) : 0u;
         if (c0 + i >= k.C) x[i] = make_uint4(0u, 0u, 0u, 0u);
     }
+}
+
+__device__ inline void load_task16(const TileCtx& k, int64_t idx, uint4 x[4], const uint32_t e[4],
+                                   uint8_t* tile, uint8_t* ftile, bool want_flags, bool or_flags,
+                                   uint32_t* exc_pos, uint32_t* exc_n) {
+    const int tq_log = k.tw_log - 2;
+    const int64_t q4 = idx >> tq_log;
+    const int w16 = (int)(idx & ((1 << tq_log) - 1));
+    const int64_t c0 = 4 * q4;
     uint32_t tf[4][4] = {};   // TD flag bytes of dwords mapped here (worklist full)
     if (k.n_td > 0) {
 #pragma unroll
         for (int i = 0; i < 4; i++) {
             if (c0 + i >= k.C) continue;
-            const uint32_t e = k.rec[(c0 + i) * k.n_td + (k.n_td - 1)];
-            const uint32_t klo = klo_of(e & 255u), khi = khi_of((e >> 8) & 255u);
+            const uint32_t klo = klo_of(e[i] & 255u), khi = khi_of((e[i] >> 8) & 255u);
             uint32_t* xi = &x[i].x;
             const uint32_t m0 = outside_mask(xi[0], klo, khi), m1 = outside_mask(xi[1], klo, khi);
             const uint32_t m2 = outside_mask(xi[2], klo, khi), m3 = outside_mask(xi[3], klo, khi);
@@ -588,7 +591,7 @@ __device__ inline void tile_store_task16(const TileCtx& k, int64_t idx, const ui
 #undef RFIM_S16
 #pragma unroll
     for (int i = 0; i < 4; i++)
-        if (c0 + i < k.C) *(uint4*)(k.out + (c0 + i) * k.stride + k.t0 + 16 * w16) = x[i];
+        if (c0 + i < k.C) st_global<uint4>(k.out + (c0 + i) * k.stride + k.t0 + 16 * w16, x[i]);
     if (want_flags) {
         for (int j = 0; j < 4; j++) {
             uint32_t fy[4], fx[4];
@@ -976,8 +979,20 @@ __global__ __launch_bounds__(kBlock) void k_fused_u8(const DevBeam* __restrict__
     // ---- phase 1: rows in, TD fast check, transposed into LDS
     const bool wide = interior && (k.Tt & 15) == 0;
     if (wide) {
-        for (int64_t idx = tid; idx < ntask / 4; idx += kBlock)
-            tile_load_task16(k, idx, tile, ftile, want_flags, or_flags, exc_pos, &exc_n);
+        constexpr int kPre = 3;   // tasks per thread whose loads are in flight together
+        const int64_t n = ntask / 4;
+        for (int64_t b0 = tid; b0 < n; b0 += kPre * kBlock) {
+            uint4 xs[kPre][4];
+            uint32_t es[kPre][4];
+#pragma unroll
+            for (int u = 0; u < kPre; u++)
+                if (b0 + u * kBlock < n) fetch16(k, b0 + u * kBlock, xs[u], es[u]);
+#pragma unroll
+            for (int u = 0; u < kPre; u++)
+                if (b0 + u * kBlock < n)
+                    load_task16(k, b0 + u * kBlock, xs[u], es[u], tile, ftile, want_flags, or_flags, exc_pos,
+                                &exc_n);
+        }
     } else if (interior) {
         for (int64_t idx = tid; idx < ntask; idx += kBlock)
             tile_load_task<true>(k, idx, tile, ftile, want_flags, or_flags, exc_pos, &exc_n);
@@ -988,7 +1003,50 @@ __global__ __launch_bounds__(kBlock) void k_fused_u8(const DevBeam* __restrict__
     __syncthreads();
 
     // ---- TD exceptions: full composite map for the dwords that need it
-    if (k.n_td > 0) {
+    if (k.n_td > 0 && k.n_td <= 4) {
+        // a thread's (at most kExcCap / kBlock) exceptions: every record they
+        // need is requested before any is used
+        constexpr int kPer = (kExcCap + kBlock - 1) / kBlock;
+        const uint32_t ne = min(exc_n, (uint32_t)kExcCap);   // the rest were mapped in phase 1
+        uint32_t r[kPer][4];
+#pragma unroll
+        for (int u = 0; u < kPer; u++) {
+            const uint32_t e = tid + u * kBlock;
+            const uint32_t* rp = k.rec + (int64_t)(e < ne ? exc_pos[e] >> 8 : 0u) * k.n_td;
+#pragma unroll
+            for (int j = 0; j < 4; j++) r[u][j] = (e < ne && j < k.n_td) ? ld_global<uint32_t>(rp + j) : 0u;
+        }
+#pragma unroll
+        for (int u = 0; u < kPer; u++) {
+            const uint32_t e = tid + u * kBlock;
+            if (e >= ne) continue;
+            const uint32_t pos = exc_pos[e];
+            const int64_t c = pos >> 8;
+            const int w = pos & 255;
+            uint32_t xv = 0;   // the tile still holds this dword's raw bytes
+            for (int j = 0; j < 4; j++) xv |= (uint32_t)tile[(size_t)(4 * w + j) * k.Cp + c] << (8 * j);
+            uint32_t nv = 0, f4 = 0;
+#pragma unroll
+            for (int b8 = 0; b8 < 4; b8++) {
+                const uint32_t x = (xv >> (8 * b8)) & 255u;
+                uint32_t out = x, f = 0;
+                // the first step whose interval excludes x decides (intervals nest)
+#pragma unroll
+                for (int j = 3; j >= 0; j--) {
+                    if (j >= k.n_td) continue;
+                    const uint32_t rj = r[u][j];
+                    if (x < (rj & 255u) || x > ((rj >> 8) & 255u)) {
+                        out = (rj >> 16) & 255u;
+                        f = rj >> 24;
+                    }
+                }
+                nv |= out << (8 * b8);
+                f4 |= f << (8 * b8);
+            }
+            put_dword_transposed(tile, k, c, w, nv);
+            if (want_flags) or_dword_transposed(ftile, k, c, w, f4);
+        }
+    } else if (k.n_td > 0) {
         const uint32_t ne = min(exc_n, (uint32_t)kExcCap);   // the rest were mapped in phase 1
         for (uint32_t e = tid; e < ne; e += kBlock) {
             const uint32_t pos = exc_pos[e];
