@@ -523,34 +523,51 @@ __device__ inline void fetch16(const TileCtx& k, int64_t idx, uint4 x[4], uint32
     }
 }
 
-__device__ inline void load_task16(const TileCtx& k, int64_t idx, uint4 x[4], const uint32_t e[4],
+// Bit 4*i + j set when dword j of row i of the task holds a byte that a TD
+// step of the run cuts (outside the row's final nested interval).
+__device__ inline uint32_t exc_bits16(const TileCtx& k, int64_t idx, const uint4 x[4], const uint32_t e[4]) {
+    if (k.n_td <= 0) return 0u;
+    const int tq_log = k.tw_log - 2;
+    const int64_t c0 = 4 * (idx >> tq_log);
+    uint32_t bits = 0;
+#pragma unroll
+    for (int i = 0; i < 4; i++) {
+        if (c0 + i >= k.C) continue;
+        const uint32_t klo = klo_of(e[i] & 255u), khi = khi_of((e[i] >> 8) & 255u);
+        const uint32_t* xi = &x[i].x;
+#pragma unroll
+        for (int j = 0; j < 4; j++) bits |= (outside_mask(xi[j], klo, khi) != 0u ? 1u : 0u) << (4 * i + j);
+    }
+    return bits;
+}
+
+// The rest of a task: its exception dwords go to the worklist from *slot on
+// (mapped here once the worklist is full), then the 4x4 transposes into LDS.
+__device__ inline void load_task16(const TileCtx& k, int64_t idx, uint4 x[4], uint32_t bits, uint32_t* slot,
                                    uint8_t* tile, uint8_t* ftile, bool want_flags, bool or_flags,
-                                   uint32_t* exc_pos, uint32_t* exc_n) {
+                                   uint32_t* exc_pos) {
     const int tq_log = k.tw_log - 2;
     const int64_t q4 = idx >> tq_log;
     const int w16 = (int)(idx & ((1 << tq_log) - 1));
     const int64_t c0 = 4 * q4;
     uint32_t tf[4][4] = {};   // TD flag bytes of dwords mapped here (worklist full)
-    if (k.n_td > 0) {
+    uint32_t ovf = 0;         // exception dwords past the worklist's end
+    while (bits) {
+        const int b = __ffs(bits) - 1;
+        bits &= bits - 1;
+        const uint32_t sl = (*slot)++;
+        if (sl < (uint32_t)kExcCap)
+            exc_pos[sl] = ((uint32_t)(c0 + (b >> 2)) << 8) | (uint32_t)(4 * w16 + (b & 3));
+        else
+            ovf |= 1u << b;
+    }
+    if (ovf) {   // worklist full: map those here (constant indices keep x in VGPRs)
 #pragma unroll
         for (int i = 0; i < 4; i++) {
-            if (c0 + i >= k.C) continue;
-            const uint32_t klo = klo_of(e[i] & 255u), khi = khi_of((e[i] >> 8) & 255u);
             uint32_t* xi = &x[i].x;
-            const uint32_t m0 = outside_mask(xi[0], klo, khi), m1 = outside_mask(xi[1], klo, khi);
-            const uint32_t m2 = outside_mask(xi[2], klo, khi), m3 = outside_mask(xi[3], klo, khi);
-            if (m0 | m1 | m2 | m3) {
-                const uint32_t mm[4] = {m0, m1, m2, m3};
 #pragma unroll
-                for (int j = 0; j < 4; j++) {
-                    if (!mm[j]) continue;
-                    const uint32_t slot = atomicAdd(exc_n, 1u);
-                    if (slot < (uint32_t)kExcCap)
-                        exc_pos[slot] = ((uint32_t)(c0 + i) << 8) | (uint32_t)(4 * w16 + j);
-                    else   // worklist full: map here
-                        xi[j] = td_map_regs(k, c0 + i, xi[j], &tf[i][j]);
-                }
-            }
+            for (int j = 0; j < 4; j++)
+                if ((ovf >> (4 * i + j)) & 1u) xi[j] = td_map_regs(k, c0 + i, xi[j], &tf[i][j]);
         }
     }
     uint32_t a[4], y[4];
@@ -981,17 +998,40 @@ __global__ __launch_bounds__(kBlock) void k_fused_u8(const DevBeam* __restrict__
     if (wide) {
         constexpr int kPre = 3;   // tasks per thread whose loads are in flight together
         const int64_t n = ntask / 4;
-        for (int64_t b0 = tid; b0 < n; b0 += kPre * kBlock) {
+        const int lane = tid & 63;
+        // wave-uniform loop (the exception slots are reserved per wave)
+        for (int64_t w0 = tid - lane; w0 < n; w0 += kPre * kBlock) {
+            const int64_t b0 = w0 + lane;
             uint4 xs[kPre][4];
             uint32_t es[kPre][4];
 #pragma unroll
             for (int u = 0; u < kPre; u++)
                 if (b0 + u * kBlock < n) fetch16(k, b0 + u * kBlock, xs[u], es[u]);
+            uint32_t eb[kPre], cnt = 0;
+#pragma unroll
+            for (int u = 0; u < kPre; u++) {
+                eb[u] = b0 + u * kBlock < n ? exc_bits16(k, b0 + u * kBlock, xs[u], es[u]) : 0u;
+                cnt += (uint32_t)__popc(eb[u]);
+            }
+            // one worklist reservation for the wave: exclusive prefix of cnt
+            uint32_t incl = cnt;
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const uint32_t t = (uint32_t)__shfl_up((int)incl, o, 64);
+                if (lane >= o) incl += t;
+            }
+            const uint32_t total = (uint32_t)__shfl((int)incl, 63, 64);
+            uint32_t base = 0;
+            if (total) {
+                if (lane == 0) base = atomicAdd(&exc_n, total);
+                base = (uint32_t)__shfl((int)base, 0, 64);
+            }
+            uint32_t slot = base + incl - cnt;
 #pragma unroll
             for (int u = 0; u < kPre; u++)
                 if (b0 + u * kBlock < n)
-                    load_task16(k, b0 + u * kBlock, xs[u], es[u], tile, ftile, want_flags, or_flags, exc_pos,
-                                &exc_n);
+                    load_task16(k, b0 + u * kBlock, xs[u], eb[u], &slot, tile, ftile, want_flags, or_flags,
+                                exc_pos);
         }
     } else if (interior) {
         for (int64_t idx = tid; idx < ntask; idx += kBlock)
