@@ -839,13 +839,96 @@ __device__ inline uint32_t group_sum_dpp(uint32_t v) {
 
 constexpr int kB32MaxBins = 7;   // bins per lane in the 32-channel path (LDS budget bound)
 
+// kept byte values of a 32-channel bin with sum S under the cut |32 x - S| <= z:
+// ceil((S - z)/32) <= x <= floor((S + z)/32), as outside_mask constants
+__device__ inline void bin32_bounds(uint32_t S, uint32_t z, uint32_t* klo, uint32_t* khi) {
+    const int lo = -(((int)z - (int)S) >> 5);
+    const int hi = (int)((S + z) >> 5);
+    const int lc = lo < 0 ? 0 : lo, hc = hi > 255 ? 255 : hi;
+    *klo = klo_of(1);   // empty interval
+    *khi = khi_of(0);
+    if (lc <= hc) {
+        *klo = klo_of((uint32_t)lc);
+        *khi = khi_of((uint32_t)hc);
+    }
+}
+
+// lower median (rank 15) of the 32 bytes of a bin held in registers, by a
+// bitwise search: per candidate, the bytes >= it are counted 16 bits at a time
+__device__ inline uint32_t lower_median32(const uint4& a, const uint4& b) {
+    const uint32_t w[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+    uint32_t e[8], o[8];
+#pragma unroll
+    for (int i = 0; i < 8; i++) {
+        e[i] = w[i] & 0x00FF00FFu;
+        o[i] = (w[i] >> 8) & 0x00FF00FFu;
+    }
+    uint32_t prefix = 0;
+#pragma unroll
+    for (int bit = 7; bit >= 0; bit--) {
+        const uint32_t cand = prefix | (1u << bit);
+        const uint32_t kc = klo_of(cand);   // a lane >= cand gets bit 15 set
+        uint32_t ge = 0;
+#pragma unroll
+        for (int i = 0; i < 8; i++)
+            ge += (uint32_t)__popc(((e[i] + kc) & 0x80008000u) | (((o[i] + kc) & 0x80008000u) >> 1));
+        if (32u - ge <= 15u) prefix = cand;   // at most 15 bytes below cand
+    }
+    return prefix;
+}
+
+// replaces the bytes of the bin at `off` that the masks select by r (flags
+// too); returns how many were replaced
+__device__ inline uint32_t bin32_replace(uint8_t* tile, uint8_t* ftile, uint32_t off, uint4 a, uint4 b,
+                                         const uint32_t m[8], uint32_t r, uint32_t fbit, bool want_flags) {
+    const uint32_t rr = r * 0x01010101u;
+    a.x = (a.x & ~m[0]) | (rr & m[0]);
+    a.y = (a.y & ~m[1]) | (rr & m[1]);
+    a.z = (a.z & ~m[2]) | (rr & m[2]);
+    a.w = (a.w & ~m[3]) | (rr & m[3]);
+    b.x = (b.x & ~m[4]) | (rr & m[4]);
+    b.y = (b.y & ~m[5]) | (rr & m[5]);
+    b.z = (b.z & ~m[6]) | (rr & m[6]);
+    b.w = (b.w & ~m[7]) | (rr & m[7]);
+    *(uint4*)(tile + off) = a;
+    *(uint4*)(tile + off + 16) = b;
+    if (want_flags) {
+        uint4 fa = *(const uint4*)(ftile + off);
+        uint4 fb = *(const uint4*)(ftile + off + 16);
+        fa.x |= m[0] & fbit; fa.y |= m[1] & fbit; fa.z |= m[2] & fbit; fa.w |= m[3] & fbit;
+        fb.x |= m[4] & fbit; fb.y |= m[5] & fbit; fb.z |= m[6] & fbit; fb.w |= m[7] & fbit;
+        *(uint4*)(ftile + off) = fa;
+        *(uint4*)(ftile + off + 16) = fb;
+    }
+    uint32_t n = 0;
+#pragma unroll
+    for (int i = 0; i < 8; i++) n += (uint32_t)__popc(m[i]);
+    return n >> 3;
+}
+
+__device__ inline void bin32_masks(const uint4& a, const uint4& b, uint32_t klo, uint32_t khi, uint32_t m[8]) {
+    m[0] = outside_mask(a.x, klo, khi);
+    m[1] = outside_mask(a.y, klo, khi);
+    m[2] = outside_mask(a.z, klo, khi);
+    m[3] = outside_mask(a.w, klo, khi);
+    m[4] = outside_mask(b.x, klo, khi);
+    m[5] = outside_mask(b.y, klo, khi);
+    m[6] = outside_mask(b.z, klo, khi);
+    m[7] = outside_mask(b.w, klo, khi);
+}
+
 // FD steps for bins of 32 channels: G lanes per time sample, lane q owns bins
 // q, q+G, ... (at most kB32MaxBins).  Per bin: S = sum x <= 8160 and
 // Q = sum x^2 <= 2.1e6, and sum over the bin of Z^2 = 32*(32*Q - S^2) < 2^30,
-// so everything is 32-bit until the column total.
+// so everything is 32-bit until the column total.  Median steps: bins with a
+// cut are listed (list, *list_n, at most cap entries) and their medians are
+// then taken by all lanes together, since a lane with such a bin would
+// otherwise hold its whole wave; s_z keeps each time sample's threshold.
+// Every thread of the work-group calls this (it has barriers).
 template <int G>
 __device__ inline void fd_steps_b32(const TileCtx& k, const Segment& seg, uint8_t* tile, uint8_t* ftile,
-                                    bool want_flags, bool count, unsigned long long* s_cnt) {
+                                    bool want_flags, bool count, unsigned long long* s_cnt, uint32_t* list,
+                                    uint32_t* list_n, uint32_t cap, uint32_t* s_z) {
     const int tid = threadIdx.x;
     const int tl = tid / G, q = tid % G;
     const bool valid = k.t0 + tl < k.T;
@@ -854,6 +937,11 @@ __device__ inline void fd_steps_b32(const TileCtx& k, const Segment& seg, uint8_
     const uint32_t col = (uint32_t)tl * (uint32_t)k.Cp;
     for (int s = 0; s < seg.n_fd; s++) {
         const SegStep& st = seg.fd[s];
+        const bool med = st.replace == RFIM_REPLACE_MEDIAN;
+        if (med) {
+            if (tid == 0) *list_n = 0;
+            __syncthreads();
+        }
         uint32_t Sb[kB32MaxBins];
         uint32_t zlo = 0, zhi = 0;   // per-lane sum of Z^2 as 24-bit slices
 #pragma unroll
@@ -890,6 +978,7 @@ __device__ inline void fd_steps_b32(const TileCtx& k, const Segment& seg, uint8_
         zhi = group_sum_dpp<G>(zhi);
         const uint64_t sz2 = (uint64_t)zlo + ((uint64_t)zhi << 24);
         const uint32_t z = fd_zthr_small(sz2, C, st.kx, 32u * 255u);
+        if (med && q == 0) s_z[tl] = z;
         const uint32_t fbit = st.bit >= 0 ? (1u << st.bit) * 0x01010101u : 0u;
         uint32_t nflag = 0;
 #pragma unroll
@@ -897,54 +986,52 @@ __device__ inline void fd_steps_b32(const TileCtx& k, const Segment& seg, uint8_
             const int bb = q + i * G;
             if (bb >= nb) continue;
             const uint32_t S = Sb[i];
-            // kept: |32 x - S| <= z  <=>  ceil((S - z)/32) <= x <= floor((S + z)/32)
-            const int lo = -(((int)z - (int)S) >> 5);
-            const int hi = (int)((S + z) >> 5);
-            const int lc = lo < 0 ? 0 : lo, hc = hi > 255 ? 255 : hi;
-            uint32_t klo = klo_of(1), khi = khi_of(0);   // empty interval
-            if (lc <= hc) {
-                klo = klo_of((uint32_t)lc);
-                khi = khi_of((uint32_t)hc);
-            }
+            uint32_t klo, khi;
+            bin32_bounds(S, z, &klo, &khi);
             const uint32_t off = col + (uint32_t)bb * 32u;
-            uint4 a = *(const uint4*)(tile + off);
-            uint4 b = *(const uint4*)(tile + off + 16);
-            const uint32_t m0 = outside_mask(a.x, klo, khi), m1 = outside_mask(a.y, klo, khi);
-            const uint32_t m2 = outside_mask(a.z, klo, khi), m3 = outside_mask(a.w, klo, khi);
-            const uint32_t m4 = outside_mask(b.x, klo, khi), m5 = outside_mask(b.y, klo, khi);
-            const uint32_t m6 = outside_mask(b.z, klo, khi), m7 = outside_mask(b.w, klo, khi);
-            if (m0 | m1 | m2 | m3 | m4 | m5 | m6 | m7) {
+            const uint4 a = *(const uint4*)(tile + off);
+            const uint4 b = *(const uint4*)(tile + off + 16);
+            uint32_t m[8];
+            bin32_masks(a, b, klo, khi, m);
+            if (m[0] | m[1] | m[2] | m[3] | m[4] | m[5] | m[6] | m[7]) {
                 uint32_t r;
-                if (st.replace == RFIM_REPLACE_MEDIAN) {
-                    r = lds_lower_median_u8(tile + off, 32);
+                if (med) {
+                    const uint32_t sl = atomicAdd(list_n, 1u);
+                    if (sl < cap) {   // taken later by all lanes together
+                        list[sl] = ((uint32_t)tl << 8) | (uint32_t)bb;
+                        continue;
+                    }
+                    r = lower_median32(a, b);
                 } else {
                     const uint32_t qv = S >> 5, rem = S & 31u;
                     r = qv + ((rem > 16u || (rem == 16u && (qv & 1u))) ? 1u : 0u);
                 }
-                const uint32_t rr = r * 0x01010101u;
-                a.x = (a.x & ~m0) | (rr & m0);
-                a.y = (a.y & ~m1) | (rr & m1);
-                a.z = (a.z & ~m2) | (rr & m2);
-                a.w = (a.w & ~m3) | (rr & m3);
-                b.x = (b.x & ~m4) | (rr & m4);
-                b.y = (b.y & ~m5) | (rr & m5);
-                b.z = (b.z & ~m6) | (rr & m6);
-                b.w = (b.w & ~m7) | (rr & m7);
-                *(uint4*)(tile + off) = a;
-                *(uint4*)(tile + off + 16) = b;
-                if (want_flags) {
-                    uint4 fa = *(const uint4*)(ftile + off);
-                    uint4 fb = *(const uint4*)(ftile + off + 16);
-                    fa.x |= m0 & fbit; fa.y |= m1 & fbit; fa.z |= m2 & fbit; fa.w |= m3 & fbit;
-                    fb.x |= m4 & fbit; fb.y |= m5 & fbit; fb.z |= m6 & fbit; fb.w |= m7 & fbit;
-                    *(uint4*)(ftile + off) = fa;
-                    *(uint4*)(ftile + off + 16) = fb;
-                }
-                nflag += (uint32_t)(__popc(m0) + __popc(m1) + __popc(m2) + __popc(m3) + __popc(m4) +
-                                    __popc(m5) + __popc(m6) + __popc(m7)) >> 3;
+                nflag += bin32_replace(tile, ftile, off, a, b, m, r, fbit, want_flags);
             }
         }
         if (valid && nflag && count && st.bit >= 0) atomicAdd(&s_cnt[s], (unsigned long long)nflag);
+        if (med) {
+            __syncthreads();
+            const uint32_t nl = min(*list_n, cap);
+            for (uint32_t e = tid; e < nl; e += kBlock) {
+                const uint32_t ent = list[e];
+                const uint32_t tl2 = ent >> 8, bb2 = ent & 255u;
+                const uint32_t off = tl2 * (uint32_t)k.Cp + bb2 * 32u;
+                const uint4 a = *(const uint4*)(tile + off);
+                const uint4 b = *(const uint4*)(tile + off + 16);
+                uint32_t S = 0;
+                const uint32_t w[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+#pragma unroll
+                for (int i = 0; i < 8; i++) S = __builtin_amdgcn_udot4(w[i], 0x01010101u, S, false);
+                uint32_t klo, khi;
+                bin32_bounds(S, s_z[tl2], &klo, &khi);
+                uint32_t m[8];
+                bin32_masks(a, b, klo, khi, m);
+                const uint32_t n = bin32_replace(tile, ftile, off, a, b, m, lower_median32(a, b), fbit, want_flags);
+                if (k.t0 + (int64_t)tl2 < k.T && count && st.bit >= 0) atomicAdd(&s_cnt[s], (unsigned long long)n);
+            }
+            __syncthreads();
+        }
     }
 }
 
@@ -960,6 +1047,7 @@ __global__ __launch_bounds__(kBlock) void k_fused_u8(const DevBeam* __restrict__
     __shared__ uint32_t exc_pos[kExcCap];   // (row << 8) | dword index in the tile
     __shared__ uint32_t exc_n;
     __shared__ unsigned long long s_cnt[kMaxSteps];
+    __shared__ uint32_t s_z[64];             // FD threshold per time sample of the tile
 
     const int tid = threadIdx.x;
     const int64_t g = xcd_remap(blockIdx.x, total_tiles);
@@ -1109,11 +1197,11 @@ __global__ __launch_bounds__(kBlock) void k_fused_u8(const DevBeam* __restrict__
         for (int s = 0; s < seg.n_fd; s++) b32 &= seg.fd[s].bin == 32 || (seg.fd[s].bin == 0 && k.C == 32);
         const bool cnt = counts != nullptr;
         if (b32 && k.Tt == 32)
-            fd_steps_b32<8>(k, seg, tile, ftile, want_flags, cnt, s_cnt);
+            fd_steps_b32<8>(k, seg, tile, ftile, want_flags, cnt, s_cnt, exc_pos, &exc_n, kExcCap, s_z);
         else if (b32 && k.Tt == 16)
-            fd_steps_b32<16>(k, seg, tile, ftile, want_flags, cnt, s_cnt);
+            fd_steps_b32<16>(k, seg, tile, ftile, want_flags, cnt, s_cnt, exc_pos, &exc_n, kExcCap, s_z);
         else if (b32 && k.Tt == 64)
-            fd_steps_b32<4>(k, seg, tile, ftile, want_flags, cnt, s_cnt);
+            fd_steps_b32<4>(k, seg, tile, ftile, want_flags, cnt, s_cnt, exc_pos, &exc_n, kExcCap, s_z);
         else
             fd_steps<VEC>(k, seg, tile, ftile, want_flags, cnt, s_cnt);
     }
