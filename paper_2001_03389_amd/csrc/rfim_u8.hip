@@ -158,9 +158,17 @@ __device__ inline void row_pass(const uint8_t* row, int64_t T, int lane, FD&& on
 // |n*v - S1| <= z, z being the largest integer with z^2 <= k^2 * D (the exact
 // test of the row's mean and population deviation); *lo > *hi when no value
 // is kept.  Wave-uniform.
+// floor(a / n) for |a| < 2^53 and 0 < n < 2^31: FP64 quotient, exact correction
+__device__ inline int64_t floor_div_fp(int64_t a, int64_t n) {
+    int64_t q = (int64_t)floor((double)a / (double)n);
+    while (q * n > a) q--;
+    while ((q + 1) * n <= a) q++;
+    return q;
+}
+
 __device__ inline void td_interval(uint64_t n, uint64_t S1, u128 D, const KExact& kx, int* lo, int* hi) {
     const int64_t z = (int64_t)fd_zthr(D, 1, kx, 255 * n);
-    const int64_t l = ceil_div((int64_t)S1 - z, (int64_t)n), h = floor_div((int64_t)S1 + z, (int64_t)n);
+    const int64_t l = -floor_div_fp(z - (int64_t)S1, (int64_t)n), h = floor_div_fp((int64_t)S1 + z, (int64_t)n);
     *lo = (int)(l < 0 ? 0 : (l > 256 ? 256 : l));
     *hi = (int)(h > 255 ? 255 : (h < -1 ? -1 : h));
 }
