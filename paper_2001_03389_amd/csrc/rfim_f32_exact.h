@@ -126,8 +126,29 @@ __device__ inline int k2_times(const KExact& kx, u128 V, U512* rhs) {
     return -2 * kx.ek;
 }
 
-// M * z^2 <= k^2 * R for mode-0 k; M, z below 2^128 with M * z^2 below 2^384
-__device__ inline bool mz2_le_k2r(u128 M, u128 z, const U512& rhs, int lsh) {
+// a - b for a >= b
+__device__ inline U512 u512_sub(const U512& a, const U512& b) {
+    U512 r;
+    uint64_t br = 0;
+#pragma unroll
+    for (int i = 0; i < 8; i++) {
+        const uint64_t x = a.w[i], y = b.w[i];
+        const uint64_t d = x - y - br;
+        br = (x < y || (x == y && br)) ? 1 : 0;
+        r.w[i] = d;
+    }
+    return r;
+}
+
+__device__ inline double u512_to_double(const U512& a) {
+    double v = 0.0;
+#pragma unroll
+    for (int i = 7; i >= 0; i--) v = v * 0x1p64 + (double)a.w[i];
+    return v;
+}
+
+// M * z^2 for M, z below 2^128 with M * z^2 below 2^384
+__device__ inline U512 mz2(u128 M, u128 z) {
     U512 z2 = u512_mul128(z, z);
     // (z^2) * M: z^2 < 2^256 as four limbs times M < 2^128
     U512 lhs = u512_from(0);
@@ -145,8 +166,38 @@ __device__ inline bool mz2_le_k2r(u128 M, u128 z, const U512& rhs, int lsh) {
         lhs.w[i + 2] = (uint64_t)acc;
         lhs.w[i + 3] += (uint64_t)(acc >> 64);
     }
+    return lhs;
+}
+
+// M * z^2 <= k^2 * R for mode-0 k, with rhs = k^2 R * 2^lsh
+__device__ inline bool mz2_le_k2r(u128 M, u128 z, const U512& rhs, int lsh) {
+    U512 lhs = mz2(M, z);
     if (lsh) lhs = u512_shl(lhs, lsh);
     return u512_cmp(lhs, rhs) <= 0;
+}
+
+__device__ inline double u128_to_double(u128 v) {
+    return ldexp((double)(uint64_t)(v >> 64), 64) + (double)(uint64_t)v;
+}
+
+// One Newton step on an estimate z0 of the root of M z^2 = k^2 R, from the
+// exact residual k^2 R - M z0^2 (rhs = k^2 R * 2^lsh): the FP64 estimate of a
+// root near 2^64 is only good to about 2^11, the corrected one to a unit or
+// two, which leaves the exact search a step or two.  Any z0 is acceptable
+// input and any result is acceptable output: the exact search decides.
+__device__ inline u128 zrefine(u128 M, u128 z0, const U512& rhs, int lsh, u128 zcap) {
+    if (z0 == 0 || z0 >= zcap) return z0;
+    U512 lhs = mz2(M, z0);
+    if (lsh) lhs = u512_shl(lhs, lsh);
+    const int c = u512_cmp(lhs, rhs);
+    if (c == 0) return z0;
+    const U512 d = c > 0 ? u512_sub(lhs, rhs) : u512_sub(rhs, lhs);
+    const double delta = ldexp(u512_to_double(d), -lsh) / (2.0 * u128_to_double(M) * u128_to_double(z0));
+    if (!(delta < 0x1p100)) return z0;
+    const double fl = floor(delta);
+    const u128 dz = ((u128)(uint64_t)ldexp(fl, -64) << 64) | (uint64_t)(fl - ldexp(floor(ldexp(fl, -64)), 64));
+    if (c > 0) return dz >= z0 ? 0 : z0 - dz;   // z0 too large
+    return zcap - z0 <= dz ? zcap : z0 + dz;    // z0 too small
 }
 
 // Largest z in [0, zcap] with M * z^2 <= k^2 * R (M >= 1).  The FP64 estimate
@@ -166,7 +217,7 @@ __device__ inline u128 zmax_k2(u128 M, u128 R, const KExact& kx, u128 zcap) {
         const double fl = floor(est);
         const uint64_t hi = (uint64_t)ldexp(fl, -64);
         const uint64_t lo = (uint64_t)(fl - ldexp((double)hi, 64));
-        z = ((u128)hi << 64) | lo;
+        z = zrefine(M, ((u128)hi << 64) | lo, rhs, lsh, zcap);
     }
     if (ok(z)) {
         // gallop up, then bisect in (z, z + step]
@@ -221,20 +272,6 @@ __device__ inline U512 u512_add(const U512& a, const U512& b) {
     return r;
 }
 
-// a - b for a >= b
-__device__ inline U512 u512_sub(const U512& a, const U512& b) {
-    U512 r;
-    uint64_t br = 0;
-#pragma unroll
-    for (int i = 0; i < 8; i++) {
-        const uint64_t x = a.w[i], y = b.w[i];
-        const uint64_t d = x - y - br;
-        br = (x < y || (x == y && br)) ? 1 : 0;
-        r.w[i] = d;
-    }
-    return r;
-}
-
 // a * m, truncated to 512 bits (callers keep the product below 2^512)
 __device__ inline U512 u512_mul_u128(const U512& a, u128 m) {
     const uint64_t m0 = (uint64_t)m, m1 = (uint64_t)(m >> 64);
@@ -258,12 +295,6 @@ __device__ inline U512 u512_mul_u128(const U512& a, u128 m) {
     return r;
 }
 
-__device__ inline double u512_to_double(const U512& a) {
-    double v = 0.0;
-#pragma unroll
-    for (int i = 7; i >= 0; i--) v = v * 0x1p64 + (double)a.w[i];
-    return v;
-}
 
 // Q0 * 2^48 + Q1 (Q0, Q1 below 2^128)
 __device__ inline U512 q_combine(u128 Q0, u128 Q1) {
@@ -310,7 +341,8 @@ __device__ inline u128 zmax_k2w(u128 M, const U512& R, const KExact& kx, u128 zc
         const double fl = floor(est);
         const uint64_t hi = (uint64_t)ldexp(fl, -64);
         const uint64_t lo = (uint64_t)(fl - ldexp((double)hi, 64));
-        z = ((u128)hi << 64) | lo;
+        // rb past 384 bits would take M z^2 out of mz2's range: keep the estimate
+        z = rb < 380 ? zrefine(M, ((u128)hi << 64) | lo, rhs, lsh, zcap) : (((u128)hi << 64) | lo);
     }
     if (ok(z)) {
         u128 step = 1;
