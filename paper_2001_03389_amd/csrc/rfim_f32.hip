@@ -677,63 +677,100 @@ __global__ __launch_bounds__(kF32Block) void k_fused_f32(const DevBeam* __restri
     const int64_t nitems = k.C * TQ;
     if (tid < 8) s_cnt[tid] = 0;
 
-    // ---- phase 1: rows in, TD records applied, into LDS (B > 0) or straight out
-    for (int64_t it = tid; it < nitems; it += kF32Block) {
-        const int64_t c = it / TQ;
-        const int q = (int)(it - c * TQ);
-        const int64_t t = k.t0 + 4 * q;
-        if (t >= k.T) continue;
-        const float* p = k.in + c * k.stride + t;
-        float x[4];
-        if (vec && t + 3 < k.T) {
-            const float4 f = *(const float4*)p;
-            x[0] = f.x;
-            x[1] = f.y;
-            x[2] = f.z;
-            x[3] = f.w;
-        } else {
+    // ---- phase 1: rows in, TD records applied, into LDS (B > 0) or straight out.
+    // kB1 items per thread at a time; with at most 4 TD steps their row loads
+    // and every record they need are requested before any is used.
+    constexpr int kB1 = 4;
+    const bool prefetch = k.n_td <= 4;
+    for (int64_t it0 = tid; it0 < nitems; it0 += kB1 * kF32Block) {
+        float xs[kB1][4];
+        float4 rs[kB1][4];
+        int64_t cs[kB1], ts[kB1];
+        int qs[kB1];
+        bool oks[kB1];
 #pragma unroll
-            for (int j = 0; j < 4; j++) x[j] = t + j < k.T ? p[j] : 0.0f;
-        }
-        uint32_t fb[4] = {0u, 0u, 0u, 0u};
-        for (int j = 0; j < k.n_td; j++) {
-            const float4 r4 = k.rec[c * k.n_td + j];
-            const int bit = seg.td[j].bit;
-#pragma unroll
-            for (int u = 0; u < 4; u++) {
-                const bool f = x[u] < r4.x || x[u] > r4.y;
-                x[u] = f ? r4.z : x[u];
-                if (f && bit >= 0) fb[u] |= 1u << bit;
-            }
-        }
-        if (want_flags && or_flags) {
-            const uint8_t* fp = k.flags + c * k.stride + t;
-#pragma unroll
-            for (int u = 0; u < 4; u++)
-                if (t + u < k.T) fb[u] |= fp[u];
-        }
-        if (B > 0) {
-            const int64_t pc = phys_chan(c, B);
-#pragma unroll
-            for (int u = 0; u < 4; u++) tile[(size_t)(4 * q + u) * k.Cp + pc] = x[u];
-            if (want_flags) {
-#pragma unroll
-                for (int u = 0; u < 4; u++) ftile[(size_t)(4 * q + u) * k.C + c] = (uint8_t)fb[u];
-            }
-        } else {
-            float* op = k.out + c * k.stride + t;
+        for (int u = 0; u < kB1; u++) {
+            const int64_t it = it0 + (int64_t)u * kF32Block;
+            const int64_t c = it / TQ;
+            const int q = (int)(it - c * TQ);
+            const int64_t t = k.t0 + 4 * q;
+            cs[u] = c;
+            qs[u] = q;
+            ts[u] = t;
+            oks[u] = it < nitems && t < k.T;
+            if (!oks[u]) continue;
+            const float* p = k.in + c * k.stride + t;
             if (vec && t + 3 < k.T) {
-                *(float4*)op = make_float4(x[0], x[1], x[2], x[3]);
+                const float4 f = *(const float4*)p;
+                xs[u][0] = f.x;
+                xs[u][1] = f.y;
+                xs[u][2] = f.z;
+                xs[u][3] = f.w;
             } else {
 #pragma unroll
-                for (int u = 0; u < 4; u++)
-                    if (t + u < k.T) op[u] = x[u];
+                for (int jj = 0; jj < 4; jj++) xs[u][jj] = t + jj < k.T ? p[jj] : 0.0f;
             }
-            if (want_flags) {
-                uint8_t* fp = k.flags + c * k.stride + t;
+            if (prefetch) {
 #pragma unroll
-                for (int u = 0; u < 4; u++)
-                    if (t + u < k.T) fp[u] = (uint8_t)fb[u];
+                for (int jj = 0; jj < 4; jj++)
+                    rs[u][jj] = jj < k.n_td ? k.rec[c * k.n_td + jj] : make_float4(0.f, 0.f, 0.f, 0.f);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kB1; u++) {
+            if (!oks[u]) continue;
+            const int64_t c = cs[u];
+            const int q = qs[u];
+            const int64_t t = ts[u];
+            float* x = xs[u];
+            uint32_t fb[4] = {0u, 0u, 0u, 0u};
+            for (int j = 0; j < k.n_td; j++) {
+                float4 r4;
+                if (prefetch) {
+                    r4 = rs[u][0];
+#pragma unroll
+                    for (int jj = 1; jj < 4; jj++)
+                        if (j == jj) r4 = rs[u][jj];
+                } else {
+                    r4 = k.rec[c * k.n_td + j];
+                }
+                const int bit = seg.td[j].bit;
+#pragma unroll
+                for (int uu = 0; uu < 4; uu++) {
+                    const bool f = x[uu] < r4.x || x[uu] > r4.y;
+                    x[uu] = f ? r4.z : x[uu];
+                    if (f && bit >= 0) fb[uu] |= 1u << bit;
+                }
+            }
+            if (want_flags && or_flags) {
+                const uint8_t* fp = k.flags + c * k.stride + t;
+#pragma unroll
+                for (int uu = 0; uu < 4; uu++)
+                    if (t + uu < k.T) fb[uu] |= fp[uu];
+            }
+            if (B > 0) {
+                const int64_t pc = phys_chan(c, B);
+#pragma unroll
+                for (int uu = 0; uu < 4; uu++) tile[(size_t)(4 * q + uu) * k.Cp + pc] = x[uu];
+                if (want_flags) {
+#pragma unroll
+                    for (int uu = 0; uu < 4; uu++) ftile[(size_t)(4 * q + uu) * k.C + c] = (uint8_t)fb[uu];
+                }
+            } else {
+                float* op = k.out + c * k.stride + t;
+                if (vec && t + 3 < k.T) {
+                    *(float4*)op = make_float4(x[0], x[1], x[2], x[3]);
+                } else {
+#pragma unroll
+                    for (int uu = 0; uu < 4; uu++)
+                        if (t + uu < k.T) op[uu] = x[uu];
+                }
+                if (want_flags) {
+                    uint8_t* fp = k.flags + c * k.stride + t;
+#pragma unroll
+                    for (int uu = 0; uu < 4; uu++)
+                        if (t + uu < k.T) fp[uu] = (uint8_t)fb[uu];
+                }
             }
         }
     }

@@ -217,7 +217,8 @@ __device__ inline u128 zmax_k2(u128 M, u128 R, const KExact& kx, u128 zcap) {
         const double fl = floor(est);
         const uint64_t hi = (uint64_t)ldexp(fl, -64);
         const uint64_t lo = (uint64_t)(fl - ldexp((double)hi, 64));
-        z = zrefine(M, ((u128)hi << 64) | lo, rhs, lsh, zcap);
+        z = ((u128)hi << 64) | lo;
+        if (est >= 0x1p50) z = zrefine(M, z, rhs, lsh, zcap);   // below 2^50 the estimate is within a unit
     }
     if (ok(z)) {
         // gallop up, then bisect in (z, z + step]
@@ -342,7 +343,8 @@ __device__ inline u128 zmax_k2w(u128 M, const U512& R, const KExact& kx, u128 zc
         const uint64_t hi = (uint64_t)ldexp(fl, -64);
         const uint64_t lo = (uint64_t)(fl - ldexp((double)hi, 64));
         // rb past 384 bits would take M z^2 out of mz2's range: keep the estimate
-        z = rb < 380 ? zrefine(M, ((u128)hi << 64) | lo, rhs, lsh, zcap) : (((u128)hi << 64) | lo);
+        z = ((u128)hi << 64) | lo;
+        if (est >= 0x1p50 && rb < 380) z = zrefine(M, z, rhs, lsh, zcap);
     }
     if (ok(z)) {
         u128 step = 1;
