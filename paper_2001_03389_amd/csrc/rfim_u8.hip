@@ -1,11 +1,12 @@
 // uint8 sigma-cut kernels for gfx950 (RFIm, arXiv:2001.03389, Section IV).
 //
 // Two kernels per run of [TD steps][FD steps]:
-//  * k_td_rows_u8 -- one work-group per channel row.  Builds the row's exact
+//  * k_td_rows_u8 -- one wave per channel row (four rows per work-group), the
+//    row read in 16 KB chunks of loads.  Builds the row's exact
 //    256-bin histogram (every TD statistic of a uint8 row is a function of it:
 //    S1, S2, the lower median), then runs every TD step of the run on the
-//    histogram alone: all 256 byte values are tested against the exact cut in
-//    parallel, the counts of the values cut move to the replacement value's bin,
+//    histogram alone: the step's exact cut gives the interval of byte values
+//    kept, the counts of the values cut move to the replacement value's bin,
 //    and step j+1 sees the modified row without another pass over the data.  The
 //    result is a per-row record of the composite map: nested intervals, plus the
 //    value and flag byte a sample gets when it first falls outside them.
