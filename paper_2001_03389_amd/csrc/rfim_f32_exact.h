@@ -105,14 +105,9 @@ __device__ inline float f32_round_ratio(i128 num, uint32_t den, int e, int mode)
     return neg ? -f : f;
 }
 
-// A * 2^e rounded to float32 (RD or RU), A an integer
-__device__ inline float f32_round_int(i128 A, int e, int mode) {
-    return f32_round_ratio(A, 1u, e, mode);
-}
 
 // U512 helpers for the window decisions -------------------------------------
 
-__device__ inline U512 u512_from_u128(u128 v) { return u512_from(v); }
 
 // k^2 * V as U512 together with a left shift to apply to the other side when
 // ek < 0; returns the shift for the left-hand side.

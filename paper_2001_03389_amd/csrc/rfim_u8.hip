@@ -456,9 +456,8 @@ __device__ inline uint32_t valid_bytes(int64_t t, int64_t T) {
     return t + 3 < T ? 0xFFFFFFFFu : (t >= T ? 0u : (0xFFFFFFFFu >> (8 * (4 - (T - t)))));
 }
 
-// TD composite map of one dword of row c (4 samples) in registers; *fv gets
-// the flag bytes.  Used when the exception worklist is full.
-__device__ inline uint32_t td_map_regs(const TileCtx& k, int64_t c, uint32_t xv, uint32_t* fv) {
+// TD composite map of one dword of row c (4 samples); *fv gets the flag bytes
+__device__ inline uint32_t td_map_dword(const TileCtx& k, int64_t c, uint32_t xv, uint32_t* fv) {
     const uint32_t* rp = k.rec + c * k.n_td;
     uint32_t nv = 0, f4 = 0;
     for (int j = 0; j < 4; j++) {
@@ -494,7 +493,7 @@ __device__ inline void tile_load_task(const TileCtx& k, int64_t idx, uint8_t* ti
                 if (slot < (uint32_t)kExcCap) {
                     exc_pos[slot] = ((uint32_t)(c0 + i) << 8) | (uint32_t)w;
                 } else {   // worklist full: map here
-                    x[i] = td_map_regs(k, c, x[i], &tf[i]);
+                    x[i] = td_map_dword(k, c, x[i], &tf[i]);
                     tf[i] &= valid;
                 }
             }
@@ -576,7 +575,7 @@ __device__ inline void load_task16(const TileCtx& k, int64_t idx, uint4 x[4], ui
             uint32_t* xi = &x[i].x;
 #pragma unroll
             for (int j = 0; j < 4; j++)
-                if ((ovf >> (4 * i + j)) & 1u) xi[j] = td_map_regs(k, c0 + i, xi[j], &tf[i][j]);
+                if ((ovf >> (4 * i + j)) & 1u) xi[j] = td_map_dword(k, c0 + i, xi[j], &tf[i][j]);
         }
     }
     uint32_t a[4], y[4];
@@ -649,19 +648,6 @@ __device__ inline void tile_store_task(const TileCtx& k, int64_t idx, const uint
     }
 }
 
-// bytes of one dword as mapped by the TD composite map of row c (and flag bits)
-__device__ inline uint32_t td_map_dword(const TileCtx& k, int64_t c, uint32_t xv, uint32_t* fv) {
-    const uint32_t* rp = k.rec + c * k.n_td;
-    uint32_t nv = 0, f4 = 0;
-#pragma unroll
-    for (int j = 0; j < 4; j++) {
-        uint32_t f;
-        nv |= td_map_byte((xv >> (8 * j)) & 255u, rp, k.n_td, &f) << (8 * j);
-        f4 |= f << (8 * j);
-    }
-    *fv = f4;
-    return nv;
-}
 
 __device__ inline void put_dword_transposed(uint8_t* tile, const TileCtx& k, int64_t c, int w, uint32_t v) {
 #pragma unroll
