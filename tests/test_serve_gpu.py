@@ -72,3 +72,42 @@ def test_serve_outputs_match_direct_runs(rf, mode):
     got0 = outs[0].cpu().numpy()
     np.testing.assert_array_equal(got0, oracle.pipeline(pool[0], STEPS)[0])
     s.close()
+
+
+@pytest.mark.parametrize("mode", ["per_call", "graph"])
+def test_serve_host_sourced_batches(rf, mode):
+    """Batches submitted from pinned host memory are copied in on the serve
+    stream and mitigated exactly like device-resident ones."""
+    import torch
+    dev = torch.device("cuda:0")
+    rng = np.random.default_rng(37)
+    pool = [rng.normal(90, 8, (C, T)).clip(0, 255).astype(np.uint8) for _ in range(3)]
+    for p in pool:
+        p[rng.integers(0, C, 2), :] = 245
+    host = [torch.from_numpy(p).pin_memory() for p in pool]   # new pinned allocations
+    want = []
+    for p in pool:
+        x = torch.from_numpy(p).to(dev)
+        o = torch.empty_like(x)
+        rf.rfim_pipeline_run([x], STEPS, outputs=[o])
+        want.append(o)
+    torch.cuda.synchronize()
+    say(f"serve host-sourced mode={mode}")
+    s = rf.Serve(STEPS, dtype="u8", nchan=C, nsamp=T, ring_depth=2, max_batch=3,
+                 hbm_budget=8 * C * T, max_wait_s=0.0005, deadline_s=1.0, mode=mode)
+    outs = []
+    for i in range(6):
+        d = torch.full((C, T), 9, dtype=torch.uint8, device=dev)
+        assert s.submit(i % 3, host[i % 3], arrival_s=s.now(), dst=d)
+        outs.append(d)
+        s.poll(s.now())
+    while s.stats()["completed"] < 6:
+        s.poll(s.now())
+    s.drain(s.now())
+    torch.cuda.synchronize()
+    st = s.stats()
+    say(st)
+    assert st["completed"] == 6 and st["rejected_budget"] == 0
+    for i, d in enumerate(outs):
+        assert torch.equal(d, want[i % 3])
+    s.close()
