@@ -76,6 +76,41 @@ def test_graph_replays_match_eager(rf):
     pg.close()
 
 
+def test_graph_replay_on_other_buffers(rf):
+    """A graph captured on one set of buffers, replayed on buffers of the same
+    shapes holding other data, gives that data's eager result; buffers of
+    another shape are refused before anything is launched."""
+    import torch
+    dev = torch.device("cuda:0")
+    host_a = mixed_beams()
+    rng = np.random.default_rng(45)
+    host_b = [rng.normal(60, 12, h.shape).clip(0, 255).astype(np.uint8) if h.dtype == np.uint8
+              else (rng.standard_normal(h.shape) * 3).astype(np.float32) for h in host_a]
+    ins_a = [torch.from_numpy(h).to(dev) for h in host_a]
+    ins_b = [torch.from_numpy(h).to(dev) for h in host_b]
+    outs_a = [torch.empty_like(x) for x in ins_a]
+    outs_b = [torch.empty_like(x) for x in ins_b]
+    want_b = [torch.empty_like(x) for x in ins_b]
+    rf.rfim_pipeline_run(ins_b, STEPS, outputs=want_b)
+    torch.cuda.synchronize()
+    p = rf.Plan(ins_a, STEPS, outputs=outs_a)
+    stream = torch.cuda.Stream()
+    p.capture(ins_a, outputs=outs_a, stream=stream)
+    for rep in range(3):
+        say(f"replay_on {rep}")
+        for o in outs_b:
+            o.fill_(0)
+        torch.cuda.synchronize()
+        p.replay_on(ins_b, outputs=outs_b, stream=stream)
+        stream.synchronize()
+        for i in range(len(host_b)):
+            assert torch.equal(outs_b[i], want_b[i]), f"replay {rep} beam {i}"
+    wrong = [torch.empty((x.shape[0], x.shape[1] - 4), dtype=x.dtype, device=dev) for x in ins_b]
+    with pytest.raises(rf.RfimError):
+        p.replay_on(wrong, outputs=[torch.empty_like(w) for w in wrong], stream=stream)
+    p.close()
+
+
 def test_autotune_cache_gives_identical_plan(rf, tmp_path):
     import torch
     dev = torch.device("cuda:0")
