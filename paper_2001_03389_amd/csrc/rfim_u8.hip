@@ -517,18 +517,38 @@ __device__ inline void tile_load_task(const TileCtx& k, int64_t idx, uint8_t* ti
 // dword aligned, in two halves so that a thread can issue the loads of all
 // its tasks before it waits for any: fetch16 loads the 4 rows (one 16-byte
 // load each) and their last TD records, load_task16 does the rest.
-__device__ inline void fetch16(const TileCtx& k, int64_t idx, uint4 x[4], uint32_t e[4]) {
+// The loads of NB tasks (idx = b0 + u * kBlock): every offset is computed
+// first, then every load is issued, unconditionally -- a task past n (the
+// caller ignores it) reads task n-1, and with no TD step the record read is
+// entry 0 -- so no branch splits the batch and it is in flight at once.
+// Offsets are 32-bit (the wide path is taken for beams below 4 GB only).
+// Rows past C read row C-1 here; load_task16 zeroes them.
+template <int NB>
+__device__ inline void fetch16_batch(const TileCtx& k, int64_t b0, int64_t n, uint4 (&x)[NB][4],
+                                     uint32_t (&e)[NB][4]) {
     const int tq_log = k.tw_log - 2;              // 16-sample chunks per tile row
-    const int64_t q4 = idx >> tq_log;
-    const int w16 = (int)(idx & ((1 << tq_log) - 1));
-    const int64_t c0 = 4 * q4;
+    const uint32_t cmax = (uint32_t)k.C - 1u;
+    const bool td = k.n_td > 0;
+    uint32_t xo[NB][4], eo[NB][4];
 #pragma unroll
-    for (int i = 0; i < 4; i++) {
-        const int64_t c = c0 + i < k.C ? c0 + i : k.C - 1;
-        x[i] = ld_global<uint4>(k.in + c * k.stride + k.t0 + 16 * w16);
-        e[i] = k.n_td > 0 ? ld_global<uint32_t>(k.rec + c * k.n_td + (k.n_td - 1)) : 0u;
-        if (c0 + i >= k.C) x[i] = make_uint4(0u, 0u, 0u, 0u);
+    for (int u = 0; u < NB; u++) {
+        const int64_t idx = min(b0 + (int64_t)u * kBlock, n - 1);
+        const uint32_t c0 = 4u * (uint32_t)(idx >> tq_log);
+        const uint32_t col = (uint32_t)k.t0 + 16u * ((uint32_t)idx & ((1u << tq_log) - 1u));
+#pragma unroll
+        for (int i = 0; i < 4; i++) {
+            const uint32_t c = min(c0 + (uint32_t)i, cmax);
+            xo[u][i] = c * (uint32_t)k.stride + col;
+            eo[u][i] = td ? c * (uint32_t)k.n_td + (uint32_t)(k.n_td - 1) : 0u;
+        }
     }
+#pragma unroll
+    for (int u = 0; u < NB; u++)
+#pragma unroll
+        for (int i = 0; i < 4; i++) {
+            x[u][i] = ld_global<uint4>(k.in + xo[u][i]);
+            e[u][i] = ld_global<uint32_t>(k.rec + eo[u][i]);
+        }
 }
 
 // Bit 4*i + j set when dword j of row i of the task holds a byte that a TD
@@ -558,6 +578,9 @@ __device__ inline void load_task16(const TileCtx& k, int64_t idx, uint4 x[4], ui
     const int64_t q4 = idx >> tq_log;
     const int w16 = (int)(idx & ((1 << tq_log) - 1));
     const int64_t c0 = 4 * q4;
+#pragma unroll
+    for (int i = 0; i < 4; i++)
+        if (c0 + i >= k.C) x[i] = make_uint4(0u, 0u, 0u, 0u);   // rows past C
     uint32_t tf[4][4] = {};   // TD flag bytes of dwords mapped here (worklist full)
     uint32_t ovf = 0;         // exception dwords past the worklist's end
     while (bits) {
@@ -614,9 +637,10 @@ __device__ inline void tile_store_task16(const TileCtx& k, int64_t idx, const ui
     x[0].F = a[0]; x[1].F = a[1]; x[2].F = a[2]; x[3].F = a[3];
     RFIM_S16(x, 0) RFIM_S16(y, 1) RFIM_S16(z, 2) RFIM_S16(w, 3)
 #undef RFIM_S16
+    const uint32_t col = (uint32_t)k.t0 + 16u * (uint32_t)w16;   // 32-bit offsets: beams below 4 GB
 #pragma unroll
     for (int i = 0; i < 4; i++)
-        if (c0 + i < k.C) st_global<uint4>(k.out + (c0 + i) * k.stride + k.t0 + 16 * w16, x[i]);
+        if (c0 + i < k.C) st_global<uint4>(k.out + ((uint32_t)(c0 + i) * (uint32_t)k.stride + col), x[i]);
     if (want_flags) {
         for (int j = 0; j < 4; j++) {
             uint32_t fy[4], fx[4];
@@ -1077,7 +1101,7 @@ __global__ __launch_bounds__(kBlock) void k_fused_u8(const DevBeam* __restrict__
     __syncthreads();
 
     // ---- phase 1: rows in, TD fast check, transposed into LDS
-    const bool wide = interior && (k.Tt & 15) == 0;
+    const bool wide = interior && (k.Tt & 15) == 0 && (uint64_t)k.C * (uint64_t)k.stride <= 0xFFFFFFFFull;
     if (wide) {
         constexpr int kPre = 3;   // tasks per thread whose loads are in flight together
         const int64_t n = ntask / 4;
@@ -1087,9 +1111,7 @@ __global__ __launch_bounds__(kBlock) void k_fused_u8(const DevBeam* __restrict__
             const int64_t b0 = w0 + lane;
             uint4 xs[kPre][4];
             uint32_t es[kPre][4];
-#pragma unroll
-            for (int u = 0; u < kPre; u++)
-                if (b0 + u * kBlock < n) fetch16(k, b0 + u * kBlock, xs[u], es[u]);
+            fetch16_batch<kPre>(k, b0, n, xs, es);
             uint32_t eb[kPre], cnt = 0;
 #pragma unroll
             for (int u = 0; u < kPre; u++) {
