@@ -182,7 +182,7 @@ __device__ inline void td_interval(uint64_t n, uint64_t S1, u128 D, const KExact
 // (the caller retries with every value tracked).  Median steps need nJ == 0.
 __device__ bool td_decide(const Segment& seg, uint64_t n, uint32_t hv[4], uint64_t nJ, uint64_t S1J,
                           uint64_t S2J, int jlo, int jhi, int lane, int* s_lo, int* s_hi, int* s_r,
-                          unsigned long long* s_mv, unsigned long long* cnt_row) {
+                          unsigned long long* s_mv) {
     for (int j = 0; j < seg.n_td; j++) {
         const SegStep& st = seg.td[j];
         uint64_t S1 = 0, S2 = 0;
@@ -245,9 +245,6 @@ __device__ bool td_decide(const Segment& seg, uint64_t n, uint32_t hv[4], uint64
             s_mv[j] = moved;
         }
     }
-    if (cnt_row && lane == 0)
-        for (int j = 0; j < seg.n_td; j++)
-            if (seg.td[j].bit >= 0 && s_mv[j]) atomicAdd(&cnt_row[seg.td[j].bit], s_mv[j]);
     return true;
 }
 
@@ -275,7 +272,6 @@ __global__ __launch_bounds__(kBlock) void k_td_rows_u8(const DevBeam* __restrict
     const int64_t T = bm.T;
     const uint64_t n = (uint64_t)T;
     const uint8_t* row = (const uint8_t*)bm.in + c * bm.stride;
-    unsigned long long* cnt_row = counts ? counts + (int64_t)bm.cidx * count_stride : nullptr;
     uint32_t* h = hist + (lane & (kHistCopies - 1)) * kHistPitch;
 
     auto clear_hist = [&] {
@@ -309,7 +305,7 @@ __global__ __launch_bounds__(kBlock) void k_td_rows_u8(const DevBeam* __restrict
         row_pass(row, T, lane, [&](uint32_t x) { hist4(h, x); }, [&](uint32_t x) { atomicAdd(&h[x], 1u); });
         uint32_t hv[4];
         read_hist(hv);
-        td_decide(seg, n, hv, 0, 0, 0, 1, 0, lane, s_lo, s_hi, s_r, s_mv, cnt_row);
+        td_decide(seg, n, hv, 0, 0, 0, 1, 0, lane, s_lo, s_hi, s_r, s_mv);
     }
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -340,6 +336,32 @@ __global__ __launch_bounds__(kBlock) void k_td_rows_u8(const DevBeam* __restrict
             H = 0;
         }
         rec[g * seg.n_td + j] = (uint32_t)L | ((uint32_t)H << 8) | ((uint32_t)val << 16) | (f << 24);
+    }
+
+    // Flag counts.  Every row of a beam adds to the same few counters, and
+    // one atomic per row and step left the kernel waiting on those atomics
+    // for most of its time; so the work-group's rows are summed in LDS first
+    // and each step's sum goes out with one atomic per beam.
+    if (counts) {
+        __shared__ int s_beam[kRowsPerWG];
+        if (lane == 0) s_beam[wave] = bm.cidx;
+        __syncthreads();   // waves past the last row have left; they are not waited for
+        const int j = threadIdx.x;
+        if (j < seg.n_td && seg.td[j].bit >= 0) {
+            const int64_t g0 = (int64_t)blockIdx.x * kRowsPerWG;
+            const int nw = (int)min((int64_t)kRowsPerWG, total_rows - g0);
+            int cb = s_beam[0];
+            unsigned long long sum = 0;
+            for (int w = 0; w < nw; w++) {
+                if (s_beam[w] != cb) {
+                    if (sum) atomicAdd(&counts[(int64_t)cb * count_stride + seg.td[j].bit], sum);
+                    cb = s_beam[w];
+                    sum = 0;
+                }
+                sum += s_mv_all[w][j];
+            }
+            if (sum) atomicAdd(&counts[(int64_t)cb * count_stride + seg.td[j].bit], sum);
+        }
     }
 }
 

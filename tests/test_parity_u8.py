@@ -193,6 +193,30 @@ def test_td_iterations_with_shrinking_spread(rf, frac):
     check_against_oracle([x], steps, out, fl, counts=counts)
 
 
+@pytest.mark.parametrize("T", [15360, 15377, 15393, 31000, 40003])
+def test_long_rows(rf, T):
+    """Rows longer than one 16 KB chunk of the TD statistics pass, with odd
+    row strides so that rows start at every byte offset.  Near-constant rows
+    (one value in all but 0.3 % of samples), constant rows and a dense comb
+    of outliers: the replacement means depend on every count being exact."""
+    rng = np.random.default_rng(T)
+    C = 64
+    x = rng.normal(80, 10, size=(C, T + 1))
+    for r in range(0, 8):                      # near-constant rows
+        x[r] = 77 + (r & 1) * 100
+        hit = rng.random(T + 1) < 0.003
+        x[r, hit] = rng.integers(0, 256, size=int(hit.sum()))
+    x[8] = 255
+    x[9] = 0
+    x[10, :: 5] = 250                          # a dense outlier comb
+    x[11:20] += rng.normal(0, 40, size=(9, T + 1)) * (rng.random((9, T + 1)) < 0.02)
+    x = x.clip(0, 255).astype(np.uint8)
+    for steps in (synth.STEPS_ARTS40_MEAN, synth.STEPS_ARTS40_MEDIAN):
+        say(f"long rows T={T} stride={T + 1} steps={steps}")
+        out, fl, counts = gpu_run(rf, [x], steps, nsamp=[T], plan=True)
+        check_against_oracle([x], steps, out, fl, nsamp=[T], counts=counts)
+
+
 def test_td_and_fd_entry_points(rf):
     """rfim_td_sigma_cut and rfim_fd_sigma_cut are the one-step pipelines."""
     import torch
