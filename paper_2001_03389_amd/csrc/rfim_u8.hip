@@ -1050,7 +1050,10 @@ __device__ inline void fd_steps_b32(const TileCtx& k, const Segment& seg, uint8_
                 nflag += bin32_replace(tile, ftile, off, a, b, m, r, fbit, want_flags);
             }
         }
-        if (valid && nflag && count && st.bit >= 0) atomicAdd(&s_cnt[s], (unsigned long long)nflag);
+        if (count && st.bit >= 0) {   // one LDS add per wave (all lanes are here)
+            const uint32_t tot = wave_sum_u32(valid ? nflag : 0u);
+            if ((tid & 63) == 0 && tot) atomicAdd(&s_cnt[s], (unsigned long long)tot);
+        }
         if (med) {
             __syncthreads();
             const uint32_t nl = min(*list_n, cap);
