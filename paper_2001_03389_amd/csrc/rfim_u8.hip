@@ -863,7 +863,10 @@ __device__ inline void fd_steps(const TileCtx& k, const Segment& seg, uint8_t* t
                 }
             }
         }
-        if (valid && nflag && count && st.bit >= 0) atomicAdd(&s_cnt[s], (unsigned long long)nflag);
+        if (count && st.bit >= 0) {   // one LDS add per wave (all lanes are here)
+            const uint64_t tot = wave_sum_u64_split(valid ? nflag : 0u);
+            if ((tid & 63) == 0 && tot) atomicAdd(&s_cnt[s], (unsigned long long)tot);
+        }
     }
 }
 
@@ -1022,32 +1025,57 @@ __device__ inline void fd_steps_b32(const TileCtx& k, const Segment& seg, uint8_
         if (med && q == 0) s_z[tl] = z;
         const uint32_t fbit = st.bit >= 0 ? (1u << st.bit) * 0x01010101u : 0u;
         uint32_t nflag = 0;
+        const int lane = tid & 63;
+        if (!med) {
 #pragma unroll
-        for (int i = 0; i < kB32MaxBins; i++) {
-            const int bb = q + i * G;
-            if (bb >= nb) continue;
-            const uint32_t S = Sb[i];
-            uint32_t klo, khi;
-            bin32_bounds(S, z, &klo, &khi);
-            const uint32_t off = col + (uint32_t)bb * 32u;
-            const uint4 a = *(const uint4*)(tile + off);
-            const uint4 b = *(const uint4*)(tile + off + 16);
-            uint32_t m[8];
-            bin32_masks(a, b, klo, khi, m);
-            if (m[0] | m[1] | m[2] | m[3] | m[4] | m[5] | m[6] | m[7]) {
-                uint32_t r;
-                if (med) {
-                    const uint32_t sl = atomicAdd(list_n, 1u);
-                    if (sl < cap) {   // taken later by all lanes together
-                        list[sl] = ((uint32_t)tl << 8) | (uint32_t)bb;
-                        continue;
-                    }
-                    r = lower_median32(a, b);
-                } else {
+            for (int i = 0; i < kB32MaxBins; i++) {
+                const int bb = q + i * G;
+                if (bb >= nb) continue;
+                const uint32_t S = Sb[i];
+                uint32_t klo, khi;
+                bin32_bounds(S, z, &klo, &khi);
+                const uint32_t off = col + (uint32_t)bb * 32u;
+                const uint4 a = *(const uint4*)(tile + off);
+                const uint4 b = *(const uint4*)(tile + off + 16);
+                uint32_t m[8];
+                bin32_masks(a, b, klo, khi, m);
+                if (m[0] | m[1] | m[2] | m[3] | m[4] | m[5] | m[6] | m[7]) {
                     const uint32_t qv = S >> 5, rem = S & 31u;
-                    r = qv + ((rem > 16u || (rem == 16u && (qv & 1u))) ? 1u : 0u);
+                    const uint32_t r = qv + ((rem > 16u || (rem == 16u && (qv & 1u))) ? 1u : 0u);
+                    nflag += bin32_replace(tile, ftile, off, a, b, m, r, fbit, want_flags);
                 }
-                nflag += bin32_replace(tile, ftile, off, a, b, m, r, fbit, want_flags);
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < kB32MaxBins; i++) {
+                const int bb = q + i * G;
+                const uint32_t off = col + (uint32_t)bb * 32u;
+                uint4 a = make_uint4(0u, 0u, 0u, 0u), b = a;
+                uint32_t m[8] = {0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u};
+                if (bb < nb) {
+                    uint32_t klo, khi;
+                    bin32_bounds(Sb[i], z, &klo, &khi);
+                    a = *(const uint4*)(tile + off);
+                    b = *(const uint4*)(tile + off + 16);
+                    bin32_masks(a, b, klo, khi, m);
+                }
+                const bool cut = (m[0] | m[1] | m[2] | m[3] | m[4] | m[5] | m[6] | m[7]) != 0u;
+                // list slots for this round's cut bins: one LDS add per wave
+                const uint64_t bal = __ballot(cut);
+                uint32_t base = 0;
+                if (bal) {
+                    const int leader = __ffsll((unsigned long long)bal) - 1;
+                    if (lane == leader) base = atomicAdd(list_n, (uint32_t)__popcll(bal));
+                    base = (uint32_t)__shfl((int)base, leader, 64);
+                }
+                const uint32_t sl =
+                    base + __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
+                if (!cut) continue;
+                if (sl < cap) {   // taken later by all lanes together
+                    list[sl] = ((uint32_t)tl << 8) | (uint32_t)bb;
+                    continue;
+                }
+                nflag += bin32_replace(tile, ftile, off, a, b, m, lower_median32(a, b), fbit, want_flags);
             }
         }
         if (count && st.bit >= 0) {   // one LDS add per wave (all lanes are here)
@@ -1057,6 +1085,7 @@ __device__ inline void fd_steps_b32(const TileCtx& k, const Segment& seg, uint8_
         if (med) {
             __syncthreads();
             const uint32_t nl = min(*list_n, cap);
+            uint32_t nlist = 0;
             for (uint32_t e = tid; e < nl; e += kBlock) {
                 const uint32_t ent = list[e];
                 const uint32_t tl2 = ent >> 8, bb2 = ent & 255u;
@@ -1072,7 +1101,11 @@ __device__ inline void fd_steps_b32(const TileCtx& k, const Segment& seg, uint8_
                 uint32_t m[8];
                 bin32_masks(a, b, klo, khi, m);
                 const uint32_t n = bin32_replace(tile, ftile, off, a, b, m, lower_median32(a, b), fbit, want_flags);
-                if (k.t0 + (int64_t)tl2 < k.T && count && st.bit >= 0) atomicAdd(&s_cnt[s], (unsigned long long)n);
+                if (k.t0 + (int64_t)tl2 < k.T) nlist += n;
+            }
+            if (count && st.bit >= 0) {   // one LDS add per wave
+                const uint32_t tot = wave_sum_u32(nlist);
+                if (lane == 0 && tot) atomicAdd(&s_cnt[s], (unsigned long long)tot);
             }
             __syncthreads();
         }
