@@ -193,6 +193,25 @@ def test_td_iterations_with_shrinking_spread(rf, frac):
     check_against_oracle([x], steps, out, fl, counts=counts)
 
 
+@pytest.mark.parametrize("seed", range(6))
+def test_flag_counts_rows_across_work_groups(rf, seed):
+    """Per-step flag counts with beams whose channel counts are not multiples
+    of four: the TD statistics kernel sums the counts of the rows it handles
+    together (up to four) before adding them to the beam's counter, so some
+    groups of rows span two beams and the last one is short."""
+    rng = np.random.default_rng(900 + seed)
+    C = int(rng.choice([1, 3, 5, 6, 7]))
+    steps = [synth.td(float(rng.choice([1.5, 2.0, 2.75]))), synth.td(2.0, "median"), synth.td(1.5),
+             synth.fd(2.0, C)]
+    beams = []
+    for _ in range(int(rng.integers(2, 6))):
+        T = int(rng.choice([64, 300, 1000, 4097]))
+        beams.append(rng.normal(100, 15, size=(C, T)).clip(0, 255).astype(np.uint8))
+    say(f"seed={seed} C={C} shapes={[b.shape for b in beams]} steps={steps}")
+    out, fl, counts = gpu_run(rf, beams, steps, plan=True)
+    check_against_oracle(beams, steps, out, fl, counts=counts)
+
+
 @pytest.mark.parametrize("T", [15360, 15377, 15393, 31000, 40003])
 def test_long_rows(rf, T):
     """Rows longer than one 16 KB chunk of the TD statistics pass, with odd
