@@ -1,16 +1,19 @@
 #!/usr/bin/env python3
 """Throughput of the RFI-mitigation hot path on one MI355X.
 
-One step = one rfim_pipeline_run over the whole 40-beam batch (1536 channels x
-12500 samples uint8 per beam): TD 4.0, 3.5, 3.25 then FD 3.0, 2.75 with
-32-channel bins, mean replacement, out-of-place, inputs resident in HBM.
-Prints one JSON line: GB/s mitigated (input bytes / time), the roofline of the
-dominant kernel (algorithmic bytes / its HIP-event duration), a real-time
-serve sweep (largest number of beams, one 1536 x 12500 batch per 1.024 s per
-beam, whose p99 latency stays within the batch period; graph form beside the
-per-call form) and the CPU oracle timed on a bounded sample of the workload.
---workload uneven72 / stress16 measure the batched uneven mixed-dtype
-workload (autotuned, HIP-graph replay) and the float32 stress workload.
+Default line: the largest single-GPU workload, 16 beams x 4096 channels x
+65536 samples float32 (17.2 GB), TD 4.0/3.5/3.25/3.25 + FD 3.0/2.75/2.75 with
+32-channel bins, median replacement, out of place, inputs resident in HBM.
+One step = one rfim_pipeline_run over the whole batch.  The JSON line carries
+GB/s mitigated (input bytes / time), the roofline of the dominant kernel
+(algorithmic bytes / its HIP-event launch duration), the CPU oracle on a
+bounded sample (one pinned core, best of 3, and one process per core), and
+sub-records with their own roofline: the 40-beam uint8 workload (mean and
+median), the 72-descriptor uneven call (auto-tuned, HIP-graph replay), one
+beam per call and per graph replay, and the real-time serve sweep (largest
+number of beams, one 1536 x 12500 batch per 1.024 s per beam, whose p99
+latency stays within the batch period; graph form beside the per-call form).
+--workload NAME measures one workload only (for profiling runs).
 """
 from __future__ import annotations
 
@@ -219,11 +222,13 @@ def single_beam(rf, torch, dev, reps=200):
             "gbs_graph_replay": round(nb / (ms_graph * 1e-3) / 1e9, 1), "reps": reps}
 
 
-def serve_sweep(rf, torch, dev, budget_s=45.0):
+def serve_sweep(rf, torch, dev, budget_s=45.0, confirm_s=12.0):
     """Largest beam count each form sustains at the real-time rate (p99 within
     the 1.024 s batch period), per-call form beside the graph form, on the
     1536 x 12500 uint8 TD 3.25 + FD 2.75 workload; batches come from a device
-    pool of distinct synthetic batches."""
+    pool of distinct synthetic batches.  A bisection over 2.5 s trials finds
+    the boundary; the largest sustained count is then confirmed by a trial of
+    confirm_s seconds (over 10 batch periods), stepping down until one holds."""
     import synth
     steps = list(synth.STEPS_ARTS1)
     specs = [synth.BeamSpec("u8", 1536, 12500, 4, b) for b in range(8)]
@@ -231,7 +236,7 @@ def serve_sweep(rf, torch, dev, budget_s=45.0):
     torch.cuda.synchronize()
     out = {"workload": "1536 ch x 12500 samples uint8 per arrival (19.2 MB), Poisson arrivals, "
                        "one batch per 1.024 s per beam, TD 3.25 + FD 2.75 (32-ch bins), mean",
-           "deadline_s": 1.024, "window_s": 2.5}
+           "deadline_s": 1.024, "search_window_s": 2.5, "confirm_window_s": confirm_s, "max_batch": 32}
     t_start = time.time()
     for form in ("graph", "per_call"):
         lo, hi, best = 0, None, None
@@ -252,121 +257,197 @@ def serve_sweep(rf, torch, dev, budget_s=45.0):
                 break
             else:
                 n = (lo + hi) // 2
-        out[form] = {"max_realtime_beams": lo, "at_max": best, "first_unsustained": hi,
-                     "max_beams_p99_within_10ms": stage}
+        # confirmation over more than 10 batch periods, stepping down by 10 %
+        confirmed, crec = 0, None
+        n = lo
+        for _ in range(3):
+            if n <= 0:
+                break
+            ok, rec = serve_trial(rf, torch, steps, pool, n, form, 1.024, confirm_s, seed=n + 1)
+            log(f"  serve {form} N={n} ({confirm_s:.0f} s): {'ok' if ok else 'no'} {rec}")
+            if ok:
+                confirmed, crec = n, rec
+                break
+            n = int(n * 0.9) // 100 * 100
+        out[form] = {"max_realtime_beams": confirmed, "at_max": crec, "search_max": lo, "search_at_max": best,
+                     "first_unsustained": hi, "max_beams_p99_within_10ms": stage}
     return out
 
 
-def workload_of(args):
-    """(beam specs, steps, description, dtype) of the workload named by args."""
+WORKLOADS = ("stress16", "arts40", "uneven72")
+
+
+def workload_of(name, replace="mean", inplace=False, beams=40, no_autotune=False):
+    """(beam specs, steps, description, dtype) of a named workload."""
     import synth
-    if args.workload == "arts40":
-        specs = synth.arts40_specs(args.beams)
-        steps = synth.STEPS_ARTS40_MEAN if args.replace == "mean" else synth.STEPS_ARTS40_MEDIAN
+    if name == "arts40":
+        specs = synth.arts40_specs(beams)
+        steps = synth.STEPS_ARTS40_MEAN if replace == "mean" else synth.STEPS_ARTS40_MEDIAN
         desc = (f"{len(specs)} beams x 1536 ch x 12500 samples uint8, "
-                f"TD 4.0/3.5/3.25 + FD 3.0/2.75 (32-ch bins), {args.replace} replacement")
+                f"TD 4.0/3.5/3.25 + FD 3.0/2.75 (32-ch bins), {replace} replacement")
         return specs, steps, desc, "u8"
-    if args.workload == "uneven72":
+    if name == "uneven72":
         specs = synth.uneven72_specs()
         desc = ("72 beams in one call: 64 uint8 (16 each of 1536x12500, 384x25000, 4096x8192, 768x16384) + "
                 "8 float32 (2 per shape), TD 3.25 + FD 2.75 (32-ch bins), mean; "
-                + ("default tuning" if args.no_autotune else "autotuned plan") + ", HIP-graph replay")
+                + ("default tuning" if no_autotune else "autotuned plan") + ", HIP-graph replay")
         return specs, synth.STEPS_ARTS1, desc, "u8+f32"
     specs = synth.stress16_specs()
     desc = ("16 beams x 4096 ch x 65536 samples float32 (5% RFI channels, bursty impulses), "
             "TD 4.0/3.5/3.25/3.25 + FD 3.0/2.75/2.75 (32-ch bins), median, "
-            + ("in-place" if args.inplace else "out-of-place"))
+            + ("in-place" if inplace else "out-of-place"))
     return specs, synth.STEPS_STRESS, desc, "f32"
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", choices=["arts40", "uneven72", "stress16"], default="arts40")
-    ap.add_argument("--replace", choices=["mean", "median"], default="mean")
-    ap.add_argument("--beams", type=int, default=40)
-    ap.add_argument("--inplace", action="store_true", help="stress16: in-place run")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-serve", action="store_true", help="skip the real-time serve sweep")
-    ap.add_argument("--no-autotune", action="store_true",
-                    help="uneven72: default tuning parameters instead of an autotuned plan")
-    ap.add_argument("--copy-calibration", action="store_true",
-                    help="also run one plain device copy of the batch size (for counter scaling)")
-    ap.add_argument("--summarize", nargs=3, metavar=("STATS_CSV", "FETCH_CSV", "WRITE_CSV"),
-                    help="write profiles/ summaries from rocprofv3 CSV output and exit")
-    ap.add_argument("--profile-command", default="")
-    args = ap.parse_args()
-    wl_name = {"arts40": f"arts40_{args.replace}", "uneven72": "uneven72",
-               "stress16": "stress16_" + ("inplace" if args.inplace else "outofplace")}[args.workload]
-    if args.summarize:
-        specs = workload_of(args)[0]
-        summarize(*args.summarize, args.profile_command, wl_name,
-                  sum(sp.nchan * sp.nsamp * (1 if sp.dtype == "u8" else 4) for sp in specs))
-        return
-    if args.gpus != 1:
-        print(f"bench.py measures one GPU only (asked for {args.gpus}); beams are independent, "
-              "so N GPUs would each run this workload on their own share.", file=sys.stderr)
-        sys.exit(2)
+def wl_tag(name, replace="mean", inplace=False):
+    return {"arts40": f"arts40_{replace}", "uneven72": "uneven72",
+            "stress16": "stress16_" + ("inplace" if inplace else "outofplace")}[name]
 
+
+# ------------------------------------------------------------- CPU baseline
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+_CPU_SAMPLES = []   # (array, steps) per worker, set before the worker pool forks
+
+
+def _cpu_one(i):
+    import oracle
+    x, steps = _CPU_SAMPLES[i]
+    t = time.perf_counter()
+    oracle.pipeline(x, steps)
+    return time.perf_counter() - t
+
+
+def _pin(cores):
+    def init(q):
+        core = q.get()
+        os.sched_setaffinity(0, {core})
+    return init
+
+
+def cpu_sample(name):
+    """The bounded CPU sample of a workload: (list of disjoint samples for up
+    to 16 workers, steps, description).  Every sample has the shape of the
+    first; the single-core leg uses the first."""
     import numpy as np
-    import torch
-
-    import paper_2001_03389_amd as rf
     import synth
+    specs, steps, _, _ = workload_of(name)
+    if name == "stress16":
+        x = synth.make_beam(specs[0])
+        w = 512
+        samples = [np.ascontiguousarray(x[:, k * w:(k + 1) * w]) for k in range(16)]
+        desc = (f"4096 ch x {w} samples float32 (8.4 MB), time slices of stress beam 0, all 7 steps "
+                f"(TD rows of {w} samples)")
+        return samples, list(steps), desc
+    samples = [synth.make_beam(specs[b]) for b in range(16)]
+    desc = "one 1536 x 12500 uint8 beam (19.2 MB) per process, all 5 steps"
+    return samples, list(steps), desc
 
-    assert torch.cuda.is_available(), "bench needs a GPU"
-    rf.lib()
-    dev = torch.device("cuda:0")
-    # a stream of our own: a HIP graph cannot be captured on the null stream
-    stream = torch.cuda.Stream() if args.workload == "uneven72" else torch.cuda.current_stream()
 
-    specs, steps, desc, dtype = workload_of(args)
-    log(f"generating and uploading {len(specs)} beams ...")
-    t = time.time()
-    ins, host = [], []
+def cpu_baseline(name, unit_scale=1e9):
+    """Oracle throughput on the workload's bounded sample: one process pinned
+    to one core, best of 3; then one process per core (at most 16, each
+    pinned to its own core) on disjoint samples, wall-clock of the slowest.
+    Runs before torch or HIP initialise (the pool forks)."""
+    import multiprocessing as mp
+    global _CPU_SAMPLES
+    samples, steps, desc = cpu_sample(name)
+    _CPU_SAMPLES = [(x, steps) for x in samples]
+    nbytes = samples[0].nbytes
+    avail = sorted(os.sched_getaffinity(0))
+    saved = set(avail)
+    os.sched_setaffinity(0, {avail[0]})
+    try:
+        times = [_cpu_one(0) for _ in range(3)]
+    finally:
+        os.sched_setaffinity(0, saved)
+    best = min(times)
+    ncores = min(16, len(avail), len(samples))
+    ctx = mp.get_context("fork")
+    q = ctx.Queue()
+    for c in avail[:ncores]:
+        q.put(c)
+    t = time.perf_counter()
+    with ctx.Pool(ncores, initializer=_pin(avail), initargs=(q,)) as pool:
+        per = pool.map(_cpu_one, range(ncores))
+    wall = time.perf_counter() - t
+    _CPU_SAMPLES = []
+    return {"value": round(nbytes / best / unit_scale, 6), "unit": "GB/s", "cores": 1, "kind": "oracle",
+            "sample": desc + "; one process pinned to one core, best of 3",
+            "seconds_best": round(best, 3), "seconds_runs": [round(v, 3) for v in times],
+            "cpu_model": cpu_model(), "cpu_cores_available": len(avail),
+            "all_cores": {"value": round(ncores * nbytes / wall / unit_scale, 6), "unit": "GB/s",
+                          "cores": ncores, "seconds_wall": round(wall, 3),
+                          "seconds_slowest_process": round(max(per), 3),
+                          "sample": f"{ncores} processes, one per core, each on its own disjoint sample"}}
+
+
+# ------------------------------------------------------------- GPU workloads
+def upload(specs, torch, dev, keep_first=False):
+    import synth
+    ins, first = [], None
     for i, sp in enumerate(specs):
         h = synth.make_beam(sp)
         ins.append(torch.from_numpy(h).to(dev))
-        if i == 0 or (args.workload == "uneven72" and sp.dtype == "f32" and len(host) < 2):
-            host.append(h)          # kept for the CPU baseline / tuner shapes
-    shapes_all = [(x.shape[0], x.shape[1], "u8" if x.dtype == torch.uint8 else "f32") for x in ins]
-    log(f"  {time.time() - t:.1f} s")
-    outs = ins if args.inplace else [torch.empty_like(x) for x in ins]
+        if keep_first and i == 0:
+            first = h
+        del h
     torch.cuda.synchronize()
+    return ins, first
+
+
+def run_workload(rf, torch, dev, name, steps_timed, warmup, replace="mean", inplace=False, beams=40,
+                 no_autotune=False, copy_calibration=False):
+    """Times `steps_timed` pipeline steps of one workload (after `warmup`),
+    then per-kernel HIP-event durations; returns the workload's record."""
+    specs, steps, desc, dtype = workload_of(name, replace, inplace, beams, no_autotune)
+    tag = wl_tag(name, replace, inplace)
+    log(f"[{tag}] generating and uploading {len(specs)} beams ...")
+    t = time.time()
+    ins, _ = upload(specs, torch, dev)
+    log(f"  {time.time() - t:.1f} s")
+    outs = ins if inplace else [torch.empty_like(x) for x in ins]
     in_bytes = sum(x.numel() * x.element_size() for x in ins)
     nel_u8 = sum(x.numel() for x in ins if x.dtype == torch.uint8)
     nel_f32 = sum(x.numel() for x in ins if x.dtype == torch.float32)
+    # a stream of our own: a HIP graph cannot be captured on the null stream
+    stream = torch.cuda.Stream() if name == "uneven72" else torch.cuda.current_stream()
 
-    tune_info = None
-    cache = None
-    if args.workload == "uneven72" and not args.no_autotune:
+    tune_info, cache = None, None
+    if name == "uneven72" and not no_autotune:
         import tempfile
         cache = os.path.join(tempfile.mkdtemp(), "rfim_tune.json")
-        shapes = [rf.shape_beam(dt, c, t_) for c, t_, dt in shapes_all]
+        shapes = [rf.shape_beam("u8" if x.dtype == torch.uint8 else "f32", x.shape[0], x.shape[1]) for x in ins]
         t = time.time()
         best = rf.autotune(shapes, steps, cache)
         tune_info = {"params": rf.tune_lookup(cache, shapes, steps), "best_ms": round(best, 4),
                      "seconds": round(time.time() - t, 1)}
         log(f"  autotune: {tune_info}")
     plan = rf.Plan(ins, steps, outputs=outs, tune_cache=cache)
-    if args.workload == "uneven72":
+    if name == "uneven72":
         plan.capture(ins, outputs=outs, stream=stream)
         run = lambda: plan.replay(stream=stream)
     else:
         run = lambda: rf.rfim_pipeline_run(ins, steps, outputs=outs, plan=plan, stream=stream)
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         run()
     torch.cuda.synchronize()
-    log(f"warmup done ({args.warmup}); timing {args.steps} steps")
-    ms_step = time_steps(run, stream, args.steps, torch)
+    log(f"  warmup done ({warmup}); timing {steps_timed} steps")
+    ms_step = time_steps(run, stream, steps_timed, torch)
     gbs = in_bytes / (ms_step * 1e-3) / 1e9
     log(f"  {ms_step:.3f} ms/step, {gbs:.1f} GB/s mitigated")
 
     # per-kernel durations (HIP events around each launch on the launch stream)
     plan.set_timing(True)
-    for _ in range(min(args.steps, 10)):
+    for _ in range(min(steps_timed, 10)):
         rf.rfim_pipeline_run(ins, steps, outputs=outs, plan=plan, stream=stream)
     torch.cuda.synchronize()
     algo = {rf.RFIM_KERNEL_TD_ROWS_U8: nel_u8 * 1,        # reads every sample once
@@ -376,71 +457,120 @@ def main():
     kernels = kernel_table(rf, plan, ins, algo)
     plan.set_timing(False)
     log("  kernels: " + json.dumps(kernels))
-    roof = roofline_of(kernels, wl_name)
-
-    if args.copy_calibration:
+    roof = roofline_of(kernels, tag)
+    if copy_calibration:
         a = torch.empty(in_bytes, dtype=torch.uint8, device=dev)
         b = torch.empty_like(a)
         b.copy_(a)
         torch.cuda.synchronize()
         log(f"copy calibration: {in_bytes} bytes copied")
-
+        del a, b
     counts = plan.flag_counts()
     plan.close()
     del ins, outs
     torch.cuda.empty_cache()
+    rec = {"workload": desc, "value": round(gbs, 2), "unit": "GB/s", "ms_per_step": round(ms_step, 4),
+           "steps": steps_timed, "warmup": warmup, "dtype": dtype, "beams": len(specs),
+           "step_list": [[s.domain, s.k, s.replace, s.bin_size] for s in steps], "out_of_place": not inplace,
+           # algorithmic bytes: one read and one write of every sample (in place too)
+           "hbm_frac_whole_step": round(2 * in_bytes / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+           "kernels": kernels, "flags_per_step_beam0": counts[0], "roofline": roof}
+    if tune_info:
+        rec["autotune"] = tune_info
+    return rec
 
-    serve = single = None
-    if not args.no_serve and args.workload == "arts40":
-        log("single beam ...")
-        single = single_beam(rf, torch, dev)
-        log(f"  {single}")
-        log("serve sweep ...")
-        serve = serve_sweep(rf, torch, dev)
 
-    cpu = None
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", choices=list(WORKLOADS), default=None,
+                    help="measure one workload only (default: the float32 stress workload as the line, "
+                         "the others as sub-records)")
+    ap.add_argument("--replace", choices=["mean", "median"], default="mean", help="arts40 replacement")
+    ap.add_argument("--beams", type=int, default=40)
+    ap.add_argument("--inplace", action="store_true", help="stress16: in-place run")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-serve", action="store_true", help="skip the single-beam and real-time serve legs")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="uneven72: default tuning parameters instead of an autotuned plan")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run one plain device copy of the batch size (for counter scaling)")
+    ap.add_argument("--summarize", nargs=3, metavar=("STATS_CSV", "FETCH_CSV", "WRITE_CSV"),
+                    help="write profiles/ summaries from rocprofv3 CSV output and exit")
+    ap.add_argument("--profile-command", default="")
+    args = ap.parse_args()
+    primary = args.workload or "stress16"
+    tag = wl_tag(primary, args.replace, args.inplace)
+    if args.summarize:
+        specs = workload_of(primary, args.replace, args.inplace, args.beams)[0]
+        summarize(*args.summarize, args.profile_command, tag,
+                  sum(sp.nchan * sp.nsamp * (1 if sp.dtype == "u8" else 4) for sp in specs))
+        return
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for {args.gpus}); beams are independent, "
+              "so N GPUs would each run this workload on their own share.", file=sys.stderr)
+        sys.exit(2)
+
+    # CPU oracle legs first, before torch or HIP initialise (the all-cores pool forks)
+    cpu = {}
     if not args.no_cpu_baseline:
-        import oracle
-        sample = host[0]
-        if sample.dtype == np.float32 and sample.shape[1] > 2048:
-            sample = np.ascontiguousarray(sample[:, :2048])
-        t = time.time()
-        oracle.pipeline(sample, steps)
-        dt = time.time() - t
-        cpu = {"value": round(sample.nbytes / dt / 1e9, 6), "unit": "GB/s", "cores": 1,
-               "kind": "oracle", "seconds": round(dt, 2),
-               "sample": f"1 of {len(specs)} beams ({sample.shape[0]}x{sample.shape[1]} {sample.dtype}, "
-                         f"{sample.nbytes / 1e6:.1f} MB), all {len(steps)} steps, single thread"}
-        log(f"cpu oracle: {dt:.1f} s for {cpu['sample']}")
+        legs = [primary] if args.workload else ["stress16", "arts40"]
+        for name in legs:
+            log(f"cpu oracle: {name} ...")
+            cpu[name] = cpu_baseline(name)
+            log(f"  {cpu[name]}")
+
+    import torch
+
+    import paper_2001_03389_amd as rf
+
+    assert torch.cuda.is_available(), "bench needs a GPU"
+    rf.lib()
+    dev = torch.device("cuda:0")
+
+    main_rec = run_workload(rf, torch, dev, primary, args.steps, args.warmup, args.replace, args.inplace,
+                            args.beams, args.no_autotune, args.copy_calibration)
+    subs = {}
+    if args.workload is None:
+        for name, rep in (("arts40", "mean"), ("arts40", "median"), ("uneven72", "mean")):
+            r = run_workload(rf, torch, dev, name, args.steps, args.warmup, rep)
+            if name == "arts40" and rep == "mean" and "arts40" in cpu:
+                r["cpu_baseline"] = cpu["arts40"]
+            subs[wl_tag(name, rep)] = r
+    if not args.no_serve and args.workload is None:
+        log("single beam ...")
+        subs["single_beam"] = single_beam(rf, torch, dev)
+        log(f"  {subs['single_beam']}")
+        log("serve sweep ...")
+        subs["serve"] = serve_sweep(rf, torch, dev)
 
     rec = {
         "metric": "GB/s mitigated (% of HBM peak) + real-time beams/GPU at p99 batch latency",
-        "value": round(gbs, 2),
+        "value": main_rec["value"],
         "unit": "GB/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms_step, 4),
+        "ms_per_step": main_rec["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": dtype,
+        "dtype": main_rec["dtype"],
         "data": "synthetic",
-        "config": {"workload": desc, "beams": len(specs),
-                   "steps": [[s.domain, s.k, s.replace, s.bin_size] for s in steps],
-                   "out_of_place": not args.inplace},
-        "hbm_frac_whole_step": round(2 * in_bytes / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-        "kernels": kernels,
-        "flags_per_step_beam0": counts[0],
-        "roofline": roof,
-        "cpu_baseline": cpu,
+        "config": {"workload": main_rec["workload"], "beams": main_rec["beams"], "steps": main_rec["step_list"],
+                   "out_of_place": main_rec["out_of_place"]},
+        "hbm_frac_whole_step": main_rec["hbm_frac_whole_step"],
+        "kernels": main_rec["kernels"],
+        "flags_per_step_beam0": main_rec["flags_per_step_beam0"],
+        "roofline": main_rec["roofline"],
+        "cpu_baseline": cpu.get(primary),
     }
-    if tune_info:
-        rec["autotune"] = tune_info
-    if single:
-        rec["single_beam"] = single
-    if serve:
-        rec["serve"] = serve
+    if "autotune" in main_rec:
+        rec["autotune"] = main_rec["autotune"]
+    if subs:
+        rec["workloads"] = subs
     print(json.dumps(rec), flush=True)
 
 

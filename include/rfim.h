@@ -57,7 +57,8 @@ typedef enum {
     RFIM_ERR_UNSUPPORTED = -2,   /* valid, but not handled by this build */
     RFIM_ERR_OUT_OF_MEMORY = -3, /* workspace allocation failed */
     RFIM_ERR_DEVICE = -4,        /* HIP runtime or device error */
-    RFIM_ERR_BUDGET = -5         /* admission refused: HBM budget exhausted */
+    RFIM_ERR_BUDGET = -5,        /* admission refused: HBM budget exhausted */
+    RFIM_ERR_MISMATCH = -6       /* auto-tuner: a candidate configuration's output differs from the default's */
 } rfim_status;
 
 typedef enum { RFIM_U8 = 0, RFIM_F32 = 1 } rfim_dtype;
@@ -137,12 +138,17 @@ rfim_status rfim_plan_replay_on(rfim_plan* plan, const rfim_beam* beams, int32_t
 /* Auto-tuner (Section III: parameters tuned per setup and platform, the
  * configurations saved for production).  Times every candidate kernel
  * configuration for these shapes and steps on freshly allocated beams filled
- * with a deterministic pattern, rejects candidates whose outputs or flags
- * differ from the default configuration's by a single byte, and stores the
- * fastest in the JSON cache file tune_cache_path (created or updated), where
- * rfim_plan_create finds it.  Synchronises `stream`; allocates (hipMalloc)
- * twice the shapes' bytes for the duration of the call.  *best_ms (may be
- * NULL) receives the best time per run. */
+ * on the device with a deterministic pattern shaped like channelised
+ * telescope data (per-channel level and spread, narrow-band channels,
+ * broadband impulses), and stores the fastest in the JSON cache file
+ * tune_cache_path (created or updated) with the table of every candidate's
+ * time, where rfim_plan_create finds it.  Every candidate's output and flags
+ * (samples [0, nsamp) of each row) must equal the default configuration's
+ * byte for byte: the cuts are exact, so a difference is a defect, and the call
+ * returns RFIM_ERR_MISMATCH (the candidate is named on stderr) without
+ * writing the cache.  Synchronises `stream`; allocates (hipMalloc) three times
+ * the shapes' bytes for the duration of the call.  *best_ms (may be NULL)
+ * receives the best time per run. */
 rfim_status rfim_autotune(const rfim_beam* shapes, int32_t nbeams, const rfim_step* steps, int32_t nsteps,
                           const char* tune_cache_path, void* stream, double* best_ms);
 
@@ -160,6 +166,38 @@ rfim_status rfim_tune_store(const char* path, const rfim_beam* shapes, int32_t n
  * this plan, copied to host_out[nbeams * nsteps]; synchronises the plan's
  * last stream. */
 rfim_status rfim_plan_flag_counts(const rfim_plan* plan, uint64_t* host_out);
+
+/* Which frequency-domain code path a plan runs for one beam and one run of
+ * [TD steps][FD steps] (the launch shapes are the plan's; the outputs do not
+ * depend on them). */
+typedef enum {
+    RFIM_FD_PATH_NONE = 0,         /* the run has no FD step */
+    RFIM_FD_PATH_U8_BIN32_G4 = 1,  /* uint8, 32-channel bins, 4 lanes per time sample (64-sample tiles) */
+    RFIM_FD_PATH_U8_BIN32_G8 = 2,  /* uint8, 32-channel bins, 8 lanes per time sample (32-sample tiles) */
+    RFIM_FD_PATH_U8_BIN32_G16 = 3, /* uint8, 32-channel bins, 16 lanes per time sample (16-sample tiles) */
+    RFIM_FD_PATH_U8_VEC = 4,       /* uint8, any bins, 16-byte LDS reads and dot4 sums */
+    RFIM_FD_PATH_U8_BYTES = 5,     /* uint8, any bins, byte-wise */
+    RFIM_FD_PATH_F32_FAST = 6,     /* float32, bins held in registers (bin size 8, 16, 32 or 64) */
+    RFIM_FD_PATH_F32_WIDE = 7      /* float32, every time sample through the big-integer kernel */
+} rfim_fd_path;
+
+typedef struct {
+    int32_t dtype;              /* rfim_dtype */
+    int32_t fd_path;            /* rfim_fd_path */
+    int32_t tile_samples;       /* time samples per work-group of the fused TD-apply + FD pass */
+    int32_t tile_pitch;         /* LDS elements per time sample of that tile */
+    int64_t lds_bytes;          /* dynamic LDS of the fused launch that holds the beam */
+    int32_t td_threads;         /* float32 TD kernel: work-group size (0: rows go to the wide kernel); uint8: 0 */
+    int32_t td_values_per_lane; /* float32 TD kernel: row values per lane; uint8: 0 */
+    int32_t fd_bin;             /* float32 fast FD path: bin size (0: none); uint8: 0 */
+    int32_t fd_bins_per_lane;   /* float32 fast FD path: bins per lane; uint8: 0 */
+} rfim_plan_beam_info;
+
+/* Launch configuration a plan chose for beam `beam` in run `run` (the step
+ * list split into runs of consecutive TD steps followed by consecutive FD
+ * steps, in order), written to *out.  Host only, no device work.
+ * RFIM_ERR_INVALID_ARG for an index out of range. */
+rfim_status rfim_plan_describe(const rfim_plan* plan, int32_t beam, int32_t run, rfim_plan_beam_info* out);
 
 /* Kernels the library launches, for per-kernel timing. */
 typedef enum {
@@ -190,13 +228,17 @@ rfim_status rfim_plan_kernel_times(rfim_plan* plan, int32_t kind, uint64_t* laun
  * loop is driven by the caller on one clock (seconds; rfim_serve_now gives
  * the loop's own steady clock, which GPU completions are measured on):
  *   rfim_serve_submit   admits one arrival: its data (host or device memory,
- *                       one [nchan][nsamp] batch) is copied into a slot of the
- *                       loop's device pool; refused with RFIM_ERR_BUDGET when
- *                       the pool (hbm_budget bytes) is full or the beam already
- *                       has ring_depth arrivals in flight.  The mitigated batch
- *                       goes to dst (device, [nchan][nsamp], not overlapping
- *                       the pool; must stay valid until the arrival completes)
- *                       or, with dst NULL, stays in the slot;
+ *                       one contiguous [nchan][nsamp] batch of the loop's dtype)
+ *                       is copied into a slot of the loop's device pool; refused
+ *                       with RFIM_ERR_BUDGET when the pool (hbm_budget bytes) is
+ *                       full or the beam already has ring_depth arrivals in
+ *                       flight.  A device src produced on stream src_stream
+ *                       (may be NULL: src is complete already) is copied after
+ *                       the work queued there so far; a host src must stay
+ *                       unchanged until the arrival completes.  The mitigated
+ *                       batch goes to dst (device, contiguous [nchan][nsamp],
+ *                       not overlapping the pool; must stay valid until the
+ *                       arrival completes) or, with dst NULL, stays in the slot;
  *   rfim_serve_poll     harvests finished launches (latency = completion -
  *                       arrival) and launches batches of ready arrivals: a
  *                       batch goes when it holds max_batch arrivals or its
@@ -239,7 +281,7 @@ rfim_status rfim_serve_create(const rfim_serve_config* cfg, const rfim_step* ste
                               rfim_serve** out);
 double rfim_serve_now(const rfim_serve* srv);
 rfim_status rfim_serve_submit(rfim_serve* srv, int32_t beam, const void* src, int32_t src_on_host,
-                              void* dst, double arrival_s);
+                              void* src_stream, void* dst, double arrival_s);
 rfim_status rfim_serve_poll(rfim_serve* srv, double now_s, uint64_t* completed_total);
 rfim_status rfim_serve_drain(rfim_serve* srv, double now_s);
 rfim_status rfim_serve_get_stats(rfim_serve* srv, rfim_serve_stats* out);

@@ -17,7 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "librfim.so")
 
 RFIM_OK, RFIM_ERR_INVALID_ARG, RFIM_ERR_UNSUPPORTED = 0, -1, -2
-RFIM_ERR_OUT_OF_MEMORY, RFIM_ERR_DEVICE, RFIM_ERR_BUDGET = -3, -4, -5
+RFIM_ERR_OUT_OF_MEMORY, RFIM_ERR_DEVICE, RFIM_ERR_BUDGET, RFIM_ERR_MISMATCH = -3, -4, -5, -6
 RFIM_U8, RFIM_F32 = 0, 1
 RFIM_REPLACE_MEAN, RFIM_REPLACE_MEDIAN = 0, 1
 RFIM_TD, RFIM_FD = 0, 1
@@ -28,6 +28,17 @@ KERNEL_NAMES = {RFIM_KERNEL_TD_ROWS_U8: "k_td_rows_u8", RFIM_KERNEL_FUSED_U8: "k
                 RFIM_KERNEL_TD_ROWS_F32: "k_td_rows_f32", RFIM_KERNEL_FUSED_F32: "k_fused_f32",
                 RFIM_KERNEL_TD_WIDE_F32: "k_td_wide_f32", RFIM_KERNEL_FD_WIDE_F32: "k_fd_wide_f32",
                 RFIM_KERNEL_TD_TWO_F32: "k_td_two_f32", RFIM_KERNEL_FD_TWO_F32: "k_fd_two_f32"}
+
+
+FD_PATH_NAMES = {0: "none", 1: "u8_bin32_g4", 2: "u8_bin32_g8", 3: "u8_bin32_g16", 4: "u8_vec", 5: "u8_bytes",
+                 6: "f32_fast", 7: "f32_wide"}
+
+
+class rfim_plan_beam_info(ctypes.Structure):
+    _fields_ = [("dtype", ctypes.c_int32), ("fd_path", ctypes.c_int32), ("tile_samples", ctypes.c_int32),
+                ("tile_pitch", ctypes.c_int32), ("lds_bytes", ctypes.c_int64), ("td_threads", ctypes.c_int32),
+                ("td_values_per_lane", ctypes.c_int32), ("fd_bin", ctypes.c_int32),
+                ("fd_bins_per_lane", ctypes.c_int32)]
 
 
 class RfimError(RuntimeError):
@@ -98,7 +109,9 @@ def lib() -> ctypes.CDLL:
         L.rfim_serve_create.argtypes = [ctypes.POINTER(rfim_serve_config), PS, i32, ctypes.POINTER(vp)]
         L.rfim_serve_now.argtypes = [vp]
         L.rfim_serve_now.restype = dbl
-        L.rfim_serve_submit.argtypes = [vp, i32, vp, i32, vp, dbl]
+        L.rfim_serve_submit.argtypes = [vp, i32, vp, i32, vp, vp, dbl]
+        L.rfim_plan_describe.argtypes = [vp, i32, i32, ctypes.POINTER(rfim_plan_beam_info)]
+        L.rfim_plan_describe.restype = st
         L.rfim_serve_poll.argtypes = [vp, dbl, ctypes.POINTER(ctypes.c_uint64)]
         L.rfim_serve_drain.argtypes = [vp, dbl]
         L.rfim_serve_get_stats.argtypes = [vp, ctypes.POINTER(rfim_serve_stats)]
@@ -323,6 +336,15 @@ class Plan:
         _check(lib().rfim_plan_flag_counts(self.handle, buf), "rfim_plan_flag_counts")
         return [[buf[b * self.nsteps + s] for s in range(self.nsteps)] for b in range(self.nbeams)]
 
+    def describe(self, beam: int, run: int = 0) -> dict:
+        """Launch configuration chosen for one beam in one run of [TD][FD]
+        steps (rfim_plan_describe); ``fd_path`` is named as in FD_PATH_NAMES."""
+        info = rfim_plan_beam_info()
+        _check(lib().rfim_plan_describe(self.handle, int(beam), int(run), ctypes.byref(info)), "rfim_plan_describe")
+        d = {n: getattr(info, n) for n, _ in rfim_plan_beam_info._fields_}
+        d["fd_path"] = FD_PATH_NAMES.get(d["fd_path"], d["fd_path"])
+        return d
+
     def set_timing(self, enable: bool = True):
         _check(lib().rfim_plan_set_timing(self.handle, 1 if enable else 0), "rfim_plan_set_timing")
 
@@ -372,14 +394,30 @@ class Serve:
     def now(self) -> float:
         return float(lib().rfim_serve_now(self.handle))
 
-    def submit(self, beam: int, src=None, arrival_s: float = 0.0, dst=None) -> bool:
+    def _check_batch(self, t, what: str, device_only: bool = False):
+        import torch
+        want = torch.uint8 if self.cfg.dtype == RFIM_U8 else torch.float32
+        if t.dtype != want or t.numel() != self.cfg.nchan * self.cfg.nsamp or not t.is_contiguous():
+            raise ValueError(f"{what} must be a contiguous {want} tensor of {self.cfg.nchan} x {self.cfg.nsamp} "
+                             f"elements (got {t.dtype}, {tuple(t.shape)}, contiguous={t.is_contiguous()})")
+        if device_only and not t.is_cuda:
+            raise ValueError(f"{what} must be a device tensor")
+
+    def submit(self, beam: int, src=None, arrival_s: float = 0.0, dst=None, stream=None) -> bool:
         """True if admitted, False if refused (budget or the beam's ring full).
-        ``src``: a torch tensor (device or host) holding one batch, or None (mock);
-        ``dst``: device tensor for the mitigated batch (None: in place in the pool)."""
-        ptr, on_host = None, 0
+        ``src``: a contiguous torch tensor (device or host) holding one batch, or
+        None (mock); a device src is copied after the work queued so far on
+        ``stream`` (default: the current stream).  ``dst``: contiguous device
+        tensor for the mitigated batch (None: in place in the pool)."""
+        ptr, on_host, sstream = None, 0, None
         if src is not None:
+            self._check_batch(src, "src")
             ptr, on_host = src.data_ptr(), 0 if src.is_cuda else 1
-        rc = lib().rfim_serve_submit(self.handle, int(beam), ptr, on_host,
+            if src.is_cuda:
+                sstream = _stream_handle(stream)
+        if dst is not None:
+            self._check_batch(dst, "dst", device_only=True)
+        rc = lib().rfim_serve_submit(self.handle, int(beam), ptr, on_host, sstream,
                                      dst.data_ptr() if dst is not None else None, float(arrival_s))
         if rc == RFIM_ERR_BUDGET:
             return False

@@ -90,6 +90,7 @@ std::vector<Segment> segments_of(const rfim_step* steps, int32_t nsteps) {
             d.kx = make_k(steps[s].k);
             d.replace = steps[s].replace;
             d.bit = s < 8 ? s : -1;
+            d.ci = s;
             d.bin = 0;
             s++;
         }
@@ -98,6 +99,7 @@ std::vector<Segment> segments_of(const rfim_step* steps, int32_t nsteps) {
             d.kx = make_k(steps[s].k);
             d.replace = steps[s].replace;
             d.bit = s < 8 ? s : -1;
+            d.ci = s;
             d.bin = steps[s].bin_size;
             s++;
         }
@@ -365,6 +367,21 @@ bool fd_vec_ok(const rfim_beam* beams, const LaunchPlan& lp, const Segment& seg)
     return true;
 }
 
+// FD path of the uint8 fused kernel for one beam and run: the 32-channel
+// path when every FD step of the run uses 32-channel bins, the tile is 16,
+// 32 or 64 samples wide (4, 8 or 16 lanes per time sample) and every lane's
+// bins fit its registers; otherwise the general path (16-byte reads when the
+// whole launch allows them).
+int32_t fd_path_u8(const rfim_beam& b, int Tt, const Segment& seg, bool vec) {
+    if (seg.n_fd == 0) return RFIM_FD_PATH_NONE;
+    bool b32 = vec && (b.nchan % 32) == 0 && (b.nchan / 32) <= (int64_t)kB32MaxBins * (kBlock / Tt);
+    for (int s = 0; s < seg.n_fd; s++) b32 &= seg.fd[s].bin == 32 || (seg.fd[s].bin == 0 && b.nchan == 32);
+    if (b32 && Tt == 32) return RFIM_FD_PATH_U8_BIN32_G8;
+    if (b32 && Tt == 16) return RFIM_FD_PATH_U8_BIN32_G16;
+    if (b32 && Tt == 64) return RFIM_FD_PATH_U8_BIN32_G4;
+    return vec ? RFIM_FD_PATH_U8_VEC : RFIM_FD_PATH_U8_BYTES;
+}
+
 // Shapes of the float32 kernels for every float32 beam of the call.
 rfim_status plan_f32(const rfim_beam* beams, LaunchPlan* lp) {
     const int nf = (int)lp->f32_beams.size();
@@ -452,7 +469,7 @@ rfim_status make_launch_plan(const rfim_beam* beams, int32_t nbeams, const rfim_
     rfim_status fs = plan_f32(beams, lp);
     if (fs != RFIM_OK) return fs;
     auto al = [](size_t v) { return (v + 255) & ~(size_t)255; };
-    lp->count_bytes = want_counts ? al((size_t)nbeams * 8 * sizeof(unsigned long long)) : 0;
+    lp->count_bytes = want_counts ? al((size_t)nbeams * kCountStride * sizeof(unsigned long long)) : 0;
     lp->off_u8rec = lp->count_bytes;
     lp->off_f32rec = lp->off_u8rec + al((size_t)lp->u8_rows * std::max(1, lp->max_td) * 4);
     lp->off_wide = lp->off_f32rec + al((size_t)lp->f32_rows * std::max(1, lp->max_td) * 16);
@@ -521,6 +538,7 @@ void build_u8(const rfim_beam* beams, const LaunchPlan& lp, Program& pg) {
         const int sidx = (int)pg.segs.size();
         pg.segs.push_back(seg);
         const int table = (int)pg.blob.size();
+        const bool vec = fd_vec_ok(beams, lp, seg);
         int64_t row = 0, tile = 0;
         for (int j = 0; j < nu8; j++) {
             const int bi = lp.u8_beams[j];
@@ -531,6 +549,7 @@ void build_u8(const rfim_beam* beams, const LaunchPlan& lp, Program& pg) {
             d.Tt = lp.Tt[bi];
             d.Cp = lp.Cp[bi];
             d.cidx = bi;
+            d.path = fd_path_u8(beams[bi], d.Tt, seg, vec);
             row += d.C;
             tile += (d.T + d.Tt - 1) / d.Tt;
             pg.blob.push_back(d);
@@ -551,7 +570,7 @@ void build_u8(const rfim_beam* beams, const LaunchPlan& lp, Program& pg) {
         L.nbeams = nu8;
         L.total = tile;
         L.lds = lp.u8_lds;
-        L.vec = fd_vec_ok(beams, lp, seg);
+        L.vec = vec;
         pg.launches.push_back(L);
     }
 }
@@ -701,17 +720,21 @@ void build_program(const rfim_beam* beams, int32_t nbeams, const LaunchPlan& lp,
     if (want_counts) {
         Launch Z;
         Z.op = OP_ZERO_COUNTS;
-        Z.total = (int64_t)nbeams * 8;
+        Z.total = (int64_t)nbeams * kCountStride;
         pg.launches.push_back(Z);
     }
     build_u8(beams, lp, pg);
     build_f32(beams, lp, pg);
 }
 
-// Enqueues the program on `stream`; d_blob is the device copy of pg.blob.
-rfim_status enqueue(const Program& pg, const LaunchPlan& lp, const DevBeam* d_blob, Workspace& ws,
+// Enqueues the program on `stream`; d_blob is the device copy of pg.blob and
+// wbase the device workspace laid out by lp.  ws (may be null) times the
+// launches when its timing is on.
+rfim_status enqueue(const Program& pg, const LaunchPlan& lp, const DevBeam* d_blob, char* wbase, Workspace* ws,
                     hipStream_t stream, bool want_counts) {
-    char* wbase = (char*)ws.d_work;
+    auto timed = [&](int kind, auto&& launch) -> hipError_t {
+        return ws ? ws->timed_launch(kind, stream, launch) : launch();
+    };
     uint32_t* u8rec = (uint32_t*)(wbase + lp.off_u8rec);
     unsigned long long* counts = want_counts ? (unsigned long long*)wbase : nullptr;
     float4* frec = (float4*)(wbase + lp.off_f32rec);
@@ -732,53 +755,53 @@ rfim_status enqueue(const Program& pg, const LaunchPlan& lp, const DevBeam* d_bl
                 e = launch_zero_u64(counts, L.total, stream);
                 break;
             case OP_TD_U8:
-                e = ws.timed_launch(RFIM_KERNEL_TD_ROWS_U8, stream, [&] {
-                    return launch_td_rows_u8(tab, L.nbeams, L.total, seg, u8rec, counts, 8, stream);
+                e = timed(RFIM_KERNEL_TD_ROWS_U8, [&] {
+                    return launch_td_rows_u8(tab, L.nbeams, L.total, seg, u8rec, counts, kCountStride, stream);
                 });
                 break;
             case OP_FUSED_U8:
-                e = ws.timed_launch(RFIM_KERNEL_FUSED_U8, stream, [&] {
-                    return launch_fused_u8(tab, L.nbeams, L.total, seg, u8rec, L.lds, L.vec, counts, 8, stream);
+                e = timed(RFIM_KERNEL_FUSED_U8, [&] {
+                    return launch_fused_u8(tab, L.nbeams, L.total, seg, u8rec, L.lds, L.vec, counts, kCountStride, stream);
                 });
                 break;
             case OP_ZERO_WIDE:
                 e = launch_zero_u64((unsigned long long*)wide_td_n, 4, stream);
                 break;
             case OP_TD_F32:
-                e = ws.timed_launch(RFIM_KERNEL_TD_ROWS_F32, stream, [&] {
+                e = timed(RFIM_KERNEL_TD_ROWS_F32, [&] {
                     return launch_td_rows_f32(tab, L.nbeams, L.total, L.a, L.b, seg, frec, tiny_td_n, td_tiny,
-                                              wide_td_n, td_items, counts, 8, stream);
+                                              wide_td_n, td_items, counts, kCountStride, stream);
                 });
                 break;
             case OP_TD_TWO:
-                e = ws.timed_launch(RFIM_KERNEL_TD_TWO_F32, stream, [&] {
+                e = timed(RFIM_KERNEL_TD_TWO_F32, [&] {
                     return launch_td_two_f32(tab, tiny_td_n, td_tiny, L.a, seg, frec, wide_td_n, td_items, counts,
-                                             8, stream);
+                                             kCountStride, stream);
                 });
                 break;
             case OP_FD_TWO:
-                e = ws.timed_launch(RFIM_KERNEL_FD_TWO_F32, stream, [&] {
+                e = timed(RFIM_KERNEL_FD_TWO_F32, [&] {
                     return launch_fd_two_f32(tab, tiny_fd_n, fd_tiny, L.a, L.b, L.nbeams, seg, wide_fd_n, fd_items,
-                                             counts, 8, stream);
+                                             counts, kCountStride, stream);
                 });
                 break;
             case OP_LIST_ALL:
                 e = launch_list_all(L.b ? wide_fd_n : wide_td_n, L.b ? fd_items : td_items, L.a, L.total, stream);
                 break;
             case OP_TD_WIDE:
-                e = ws.timed_launch(RFIM_KERNEL_TD_WIDE_F32, stream, [&] {
-                    return launch_td_wide_f32(tab, wide_td_n, td_items, L.a, seg, frec, counts, 8, stream);
+                e = timed(RFIM_KERNEL_TD_WIDE_F32, [&] {
+                    return launch_td_wide_f32(tab, wide_td_n, td_items, L.a, seg, frec, counts, kCountStride, stream);
                 });
                 break;
             case OP_FUSED_F32:
-                e = ws.timed_launch(RFIM_KERNEL_FUSED_F32, stream, [&] {
+                e = timed(RFIM_KERNEL_FUSED_F32, [&] {
                     return launch_fused_f32(tab, L.nbeams, L.total, L.a, L.b, seg, frec, L.lds, tiny_fd_n, fd_tiny,
-                                            wide_fd_n, fd_items, counts, 8, stream);
+                                            wide_fd_n, fd_items, counts, kCountStride, stream);
                 });
                 break;
             case OP_FD_WIDE:
-                e = ws.timed_launch(RFIM_KERNEL_FD_WIDE_F32, stream, [&] {
-                    return launch_fd_wide_f32(tab, wide_fd_n, fd_items, L.a, lp.f32_maxC, seg, counts, 8, stream);
+                e = timed(RFIM_KERNEL_FD_WIDE_F32, [&] {
+                    return launch_fd_wide_f32(tab, wide_fd_n, fd_items, L.a, lp.f32_maxC, seg, counts, kCountStride, stream);
                 });
                 break;
         }
@@ -805,7 +828,7 @@ rfim_status execute(const rfim_beam* beams, int32_t nbeams, const LaunchPlan& lp
     if (st != RFIM_OK) return st;
     std::memcpy(sl->h, pg.blob.data(), sizeof(DevBeam) * pg.blob.size());
     if (hipMemcpyAsync(sl->d, sl->h, bytes, hipMemcpyHostToDevice, stream) != hipSuccess) return RFIM_ERR_DEVICE;
-    st = enqueue(pg, lp, (const DevBeam*)sl->d, ws, stream, want_counts);
+    st = enqueue(pg, lp, (const DevBeam*)sl->d, (char*)ws.d_work, &ws, stream, want_counts);
     if (st != RFIM_OK) return st;
     if (hipEventRecord(sl->ev, stream) != hipSuccess) return RFIM_ERR_DEVICE;
     sl->used = true;
@@ -878,6 +901,7 @@ const char* rfim_status_string(rfim_status s) {
         case RFIM_ERR_OUT_OF_MEMORY: return "out of memory";
         case RFIM_ERR_DEVICE: return "HIP device or runtime error";
         case RFIM_ERR_BUDGET: return "HBM budget exhausted";
+        case RFIM_ERR_MISMATCH: return "a tuning candidate's output differs from the default configuration's";
     }
     return "unknown status";
 }
@@ -1030,7 +1054,7 @@ rfim_status rfim_plan_capture(rfim_plan* plan, const rfim_beam* beams, int32_t n
         ws.timing = timing;
         return RFIM_ERR_DEVICE;
     }
-    st = enqueue(pg, plan->lp, (const DevBeam*)plan->d_blob, ws, s, true);
+    st = enqueue(pg, plan->lp, (const DevBeam*)plan->d_blob, (char*)ws.d_work, &ws, s, true);
     hipGraph_t g = nullptr;
     const hipError_t ec = hipStreamEndCapture(s, &g);
     ws.timing = timing;
@@ -1106,11 +1130,42 @@ rfim_status rfim_plan_flag_counts(const rfim_plan* plan, uint64_t* host_out) {
         return RFIM_OK;
     }
     if (hipEventSynchronize(p->ws.last_done) != hipSuccess) return RFIM_ERR_DEVICE;
-    std::vector<unsigned long long> tmp((size_t)nb * 8);
-    if (hipMemcpy(tmp.data(), (char*)p->ws.d_work, tmp.size() * 8, hipMemcpyDeviceToHost) != hipSuccess)
+    std::vector<unsigned long long> tmp((size_t)nb * kCountStride);
+    if (hipMemcpy(tmp.data(), (char*)p->ws.d_work, tmp.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost) !=
+        hipSuccess)
         return RFIM_ERR_DEVICE;
     for (int b = 0; b < nb; b++)
-        for (int s = 0; s < ns; s++) host_out[(size_t)b * ns + s] = s < 8 ? tmp[(size_t)b * 8 + s] : 0;
+        for (int s = 0; s < ns; s++) host_out[(size_t)b * ns + s] = tmp[(size_t)b * kCountStride + s];
+    return RFIM_OK;
+}
+
+rfim_status rfim_plan_describe(const rfim_plan* plan, int32_t beam, int32_t run, rfim_plan_beam_info* out) {
+    if (!plan || !out || beam < 0 || beam >= (int32_t)plan->shapes.size() || run < 0 ||
+        run >= (int32_t)plan->lp.segs.size())
+        return RFIM_ERR_INVALID_ARG;
+    const LaunchPlan& lp = plan->lp;
+    const rfim_beam& b = plan->shapes[beam];
+    const Segment& seg = lp.segs[run];
+    std::memset(out, 0, sizeof(*out));
+    out->dtype = b.dtype;
+    if (b.dtype == RFIM_U8) {
+        out->tile_samples = lp.Tt[beam];
+        out->tile_pitch = lp.Cp[beam];
+        out->lds_bytes = (int64_t)lp.u8_lds;
+        out->fd_path = fd_path_u8(b, lp.Tt[beam], seg, fd_vec_ok(plan->shapes.data(), lp, seg));
+        return RFIM_OK;
+    }
+    int j = 0;
+    while (lp.f32_beams[j] != beam) j++;
+    const LaunchPlan::F32Shape& sh = lp.f_shape[run][j];
+    out->td_threads = lp.f_nt[j];
+    out->td_values_per_lane = lp.f_vpt[j];
+    out->fd_bin = sh.B;
+    out->fd_bins_per_lane = sh.B ? sh.bpl : 0;
+    out->tile_samples = sh.B ? sh.Tt : 0;
+    out->tile_pitch = sh.B ? sh.Cp : 0;
+    out->lds_bytes = (int64_t)sh.lds;
+    out->fd_path = seg.n_fd == 0 ? RFIM_FD_PATH_NONE : (sh.B ? RFIM_FD_PATH_F32_FAST : RFIM_FD_PATH_F32_WIDE);
     return RFIM_OK;
 }
 
@@ -1146,3 +1201,4 @@ rfim_status rfim_plan_kernel_times(rfim_plan* plan, int32_t kind, uint64_t* laun
 }
 
 }  // extern "C"
+

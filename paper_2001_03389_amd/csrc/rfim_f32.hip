@@ -370,8 +370,8 @@ __device__ inline void td_row_f32(const DevBeam& bm, int64_t c, const Segment& s
             const unsigned slot = atomicAdd(bad ? wide_n : tiny_n, 1u);
             (bad ? wide_items : tiny_items)[slot] = make_int2(bm.pad, (int)c);
         }
-    } else if (counts && tid < seg.n_td && s_cnt[tid] && seg.td[tid].bit >= 0) {
-        atomicAdd(&counts[(int64_t)bm.cidx * count_stride + seg.td[tid].bit], (unsigned long long)s_cnt[tid]);
+    } else if (counts && tid < seg.n_td && s_cnt[tid]) {
+        atomicAdd(&counts[(int64_t)bm.cidx * count_stride + seg.td[tid].ci], (unsigned long long)s_cnt[tid]);
     }
     __syncthreads();   // the work-group's LDS is reused by the next row
 }
@@ -470,7 +470,7 @@ __device__ inline U512 group_add_u256(U512 v, int G) {
 // when it needs the two-window kernel; x is then not final.
 template <int B, int BPL, bool TWO>
 __device__ inline int fd_column_f32(float (&x)[BPL][B], uint32_t (&fw)[BPL][B / 4], const bool (&act)[BPL], int G2,
-                                    uint32_t C, const Segment& seg, uint64_t lc[2]) {
+                                    uint32_t C, const Segment& seg, uint64_t lc[4]) {
     uint32_t emax = 0, tmin = 0xFFFFFFFFu;
 #pragma unroll
     for (int kk = 0; kk < BPL; kk++)
@@ -488,7 +488,7 @@ __device__ inline int fd_column_f32(float (&x)[BPL][B], uint32_t (&fw)[BPL][B / 
     if (!TWO && tmin != 0xFFFFFFFFu && tmin + 1u < thr) return 2;
     const double sc = ldexp(1.0, 174 - EM), sc2 = ldexp(1.0, 198 - EM);
     const int e = TWO ? EM - 198 : EM - 174;
-    lc[0] = lc[1] = 0;
+    lc[0] = lc[1] = lc[2] = lc[3] = 0;
     for (int s = 0; s < seg.n_fd; s++) {
         const SegStep& st = seg.fd[s];
         i128 S[BPL];
@@ -562,7 +562,7 @@ __device__ inline int fd_column_f32(float (&x)[BPL][B], uint32_t (&fw)[BPL][B / 
                 x[kk][j] = f ? r : x[kk][j];
                 if (bit >= 0 && f) fw[kk][j / 4] |= (1u << bit) << (8 * (j % 4));
             }
-            if (bit >= 0) lc[bit >> 2] += (uint64_t)__popcll(fm) << (16 * (bit & 3));
+            lc[s >> 2] += (uint64_t)__popcll(fm) << (16 * (s & 3));
         }
         bad = group_or_u32(bad, G2);
         if (bad) return (bad & 1u) ? 1 : 2;
@@ -575,7 +575,7 @@ __device__ inline int fd_column_f32(float (&x)[BPL][B], uint32_t (&fw)[BPL][B / 
 template <int B, int BPL>
 __device__ void fd_fast_f32(const F32Tile& k, const Segment& seg, float* tile, uint8_t* ftile, bool want_flags,
                             unsigned* tiny_n, int2* tiny_items, unsigned* wide_n, int2* wide_items, int gidx,
-                            uint64_t cntp[2]) {
+                            uint64_t cntp[4]) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     constexpr int NW = kF32Block / 64;
     const int nbins = (int)(k.C / B);
@@ -606,7 +606,7 @@ __device__ void fd_fast_f32(const F32Tile& k, const Segment& seg, float* tile, u
 #pragma unroll
             for (int j = 0; j < B / 4; j++) fw[kk][j] = 0;
         }
-        uint64_t lc[2];
+        uint64_t lc[4];
         const int res = fd_column_f32<B, BPL, false>(x, fw, act, G2, C, seg, lc);
         if (!colok) continue;
         if (res) {
@@ -618,8 +618,8 @@ __device__ void fd_fast_f32(const F32Tile& k, const Segment& seg, float* tile, u
             }
             continue;
         }
-        cntp[0] += lc[0];
-        cntp[1] += lc[1];
+#pragma unroll
+        for (int i = 0; i < 4; i++) cntp[i] += lc[i];
 #pragma unroll
         for (int kk = 0; kk < BPL; kk++) {
             if (!act[kk]) continue;
@@ -650,7 +650,7 @@ __global__ __launch_bounds__(kF32Block) void k_fused_f32(const DevBeam* __restri
                                                          unsigned* __restrict__ wide_n, int2* __restrict__ wide_items,
                                                          unsigned long long* __restrict__ counts, int count_stride) {
     extern __shared__ __align__(16) uint8_t lds[];
-    __shared__ unsigned long long s_cnt[8];
+    __shared__ unsigned long long s_cnt[kMaxSteps];
     const int tid = threadIdx.x;
     const int64_t g = xcd_remap(blockIdx.x, total_tiles);
     const int b = find_beam_by_tile(beams, nbeams, g);
@@ -675,7 +675,7 @@ __global__ __launch_bounds__(kF32Block) void k_fused_f32(const DevBeam* __restri
     uint8_t* ftile = lds + (size_t)k.Tt * k.Cp * 4;
     const int TQ = k.Tt >> 2;   // 4-sample quads per tile row
     const int64_t nitems = k.C * TQ;
-    if (tid < 8) s_cnt[tid] = 0;
+    if (tid < kMaxSteps) s_cnt[tid] = 0;
 
     // ---- phase 1: rows in, TD records applied, into LDS (B > 0) or straight out.
     // kB1 items per thread at a time; with at most 4 TD steps their row loads
@@ -786,7 +786,7 @@ __global__ __launch_bounds__(kF32Block) void k_fused_f32(const DevBeam* __restri
     __syncthreads();
 
     // ---- phase 2: FD steps
-    uint64_t cntp[2] = {0, 0};
+    uint64_t cntp[4] = {0, 0, 0, 0};
     if (seg.n_fd > 0) {
         if constexpr (B > 0)
             fd_fast_f32<B, BPL>(k, seg, tile, ftile, want_flags, tiny_n, tiny_items, wide_n, wide_items, bm.pad, cntp);
@@ -821,13 +821,14 @@ __global__ __launch_bounds__(kF32Block) void k_fused_f32(const DevBeam* __restri
     }
     if (counts && seg.n_fd > 0) {
         // per-step counts of this lane (16-bit fields), wave sums, then global
-        for (int s = 0; s < 8; s++) {
+        for (int s = 0; s < seg.n_fd; s++) {
             const uint32_t v = (uint32_t)((cntp[s >> 2] >> (16 * (s & 3))) & 0xFFFFu);
             const uint32_t tot = wave_add_u32(v);
             if ((tid & 63) == 0 && tot) atomicAdd(&s_cnt[s], (unsigned long long)tot);
         }
         __syncthreads();
-        if (tid < 8 && s_cnt[tid]) atomicAdd(&counts[(int64_t)bm.cidx * count_stride + tid], s_cnt[tid]);
+        if (tid < seg.n_fd && s_cnt[tid])
+            atomicAdd(&counts[(int64_t)bm.cidx * count_stride + seg.fd[tid].ci], s_cnt[tid]);
     }
 }
 
@@ -865,7 +866,7 @@ __global__ __launch_bounds__(kF32Block) void k_fd_two_f32(const DevBeam* __restr
 #pragma unroll
             for (int j = 0; j < B / 4; j++) fw[kk][j] = 0;
         }
-        uint64_t lc[2];
+        uint64_t lc[4];
         const int res = fd_column_f32<B, BPL, true>(x, fw, act, G2, (uint32_t)bm.C, seg, lc);
         if (res) {
             if (lane == 0) {
@@ -887,10 +888,11 @@ __global__ __launch_bounds__(kF32Block) void k_fd_two_f32(const DevBeam* __restr
             }
         }
         if (counts) {
-            for (int sidx = 0; sidx < 8; sidx++) {
+            for (int sidx = 0; sidx < seg.n_fd; sidx++) {
                 const uint32_t v = (uint32_t)((lc[sidx >> 2] >> (16 * (sidx & 3))) & 0xFFFFu);
                 const uint32_t tot = wave_add_u32(v);
-                if (lane == 0 && tot) atomicAdd(&counts[(int64_t)bm.cidx * count_stride + sidx], (unsigned long long)tot);
+                if (lane == 0 && tot)
+                    atomicAdd(&counts[(int64_t)bm.cidx * count_stride + seg.fd[sidx].ci], (unsigned long long)tot);
             }
         }
     }
@@ -979,8 +981,8 @@ __global__ __launch_bounds__(kWideNT) void k_td_wide_f32(const DevBeam* __restri
             cnt = wave_add_u32(cnt);
             if ((tid & 63) == 0 && cnt) atomicAdd(&s_cnt, (unsigned long long)cnt);
             __syncthreads();
-            if (tid == 0 && counts && s_cnt && st.bit >= 0)
-                atomicAdd(&counts[(int64_t)bm.cidx * count_stride + st.bit], s_cnt);
+            if (tid == 0 && counts && s_cnt)
+                atomicAdd(&counts[(int64_t)bm.cidx * count_stride + st.ci], s_cnt);
             __syncthreads();
         }
     }
@@ -1091,8 +1093,8 @@ __global__ __launch_bounds__(kWideNT) void k_fd_wide_f32(const DevBeam* __restri
             cnt = wave_add_u32(cnt);
             if ((tid & 63) == 0 && cnt) atomicAdd(&s_cnt, (unsigned long long)cnt);
             __syncthreads();
-            if (tid == 0 && counts && s_cnt && st.bit >= 0)
-                atomicAdd(&counts[(int64_t)bm.cidx * count_stride + st.bit], s_cnt);
+            if (tid == 0 && counts && s_cnt)
+                atomicAdd(&counts[(int64_t)bm.cidx * count_stride + st.ci], s_cnt);
             __syncthreads();
         }
         for (int64_t c = tid; c < C; c += kWideNT) {

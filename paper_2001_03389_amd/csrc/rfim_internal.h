@@ -9,7 +9,9 @@
 namespace rfim {
 
 constexpr int kMaxSteps = 16;   // steps per pipeline (flags need <= 8)
+constexpr int kCountStride = kMaxSteps;   // flag counters per beam: one per step
 constexpr int kBlock = 256;     // work-group size of every kernel
+constexpr int kB32MaxBins = 7;  // bins per lane in the uint8 32-channel FD path
 
 // Threshold k as an exact binary fraction k = mk * 2^ek (mk odd).  mode:
 //  0 = exact comparison with mk^2 = (mk2_hi:mk2_lo) and ek,
@@ -30,6 +32,8 @@ struct SegStep {
     int32_t replace;   // rfim_replace
     int32_t bit;       // flag bit (step index in the caller's list), -1 = none
     int64_t bin;       // FD bin size (resolved per beam when 0: see DevBeam)
+    int32_t ci;        // step index in the caller's list: the flag counter of this step
+    int32_t pad;
 };
 
 // One run of consecutive TD steps followed by consecutive FD steps.
@@ -54,6 +58,8 @@ struct DevBeam {
     int32_t Cp;      // LDS elements per time sample of a tile (>= C, padded)
     int32_t cidx;    // index of the beam in the caller's list (flag counters)
     int32_t pad;     // float32: index in the call's float32 beam table (wide lists)
+    int32_t path;    // uint8: FD path of the fused kernel (rfim_fd_path), chosen on the host
+    int32_t pad2;
 };
 
 // Host launchers (defined in the .hip files).  counts (nullable) receives, per

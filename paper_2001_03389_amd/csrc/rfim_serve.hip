@@ -60,6 +60,7 @@ struct rfim_serve {
     std::vector<hipEvent_t> events;
     hipStream_t stream = nullptr;
     hipEvent_t ref = nullptr;
+    hipEvent_t src_ready = nullptr;   // orders slot copies after the caller's stream
     double t_ref = 0.0;
     std::chrono::steady_clock::time_point t0;
     std::map<int, rfim_plan*> plans;   // by batch size
@@ -81,6 +82,7 @@ struct rfim_serve {
                 if (r.done) (void)hipEventDestroy(r.done);
             for (hipEvent_t e : events) (void)hipEventDestroy(e);
             if (ref) (void)hipEventDestroy(ref);
+            if (src_ready) (void)hipEventDestroy(src_ready);
             if (pool) (void)hipFree(pool);
             if (stream) (void)hipStreamDestroy(stream);
         }
@@ -250,7 +252,8 @@ rfim_status rfim_serve_create(const rfim_serve_config* cfg, const rfim_step* ste
         }
         // device timeline: completion times are read relative to this event
         if (hipEventCreate(&s->ref) != hipSuccess || hipEventRecord(s->ref, s->stream) != hipSuccess ||
-            hipEventSynchronize(s->ref) != hipSuccess) {
+            hipEventSynchronize(s->ref) != hipSuccess ||
+            hipEventCreateWithFlags(&s->src_ready, hipEventDisableTiming) != hipSuccess) {
             delete s;
             return RFIM_ERR_DEVICE;
         }
@@ -262,8 +265,8 @@ rfim_status rfim_serve_create(const rfim_serve_config* cfg, const rfim_step* ste
 
 double rfim_serve_now(const rfim_serve* s) { return s ? s->clock_now() : 0.0; }
 
-rfim_status rfim_serve_submit(rfim_serve* s, int32_t beam, const void* src, int32_t src_on_host, void* dst,
-                              double arrival_s) {
+rfim_status rfim_serve_submit(rfim_serve* s, int32_t beam, const void* src, int32_t src_on_host, void* src_stream,
+                              void* dst, double arrival_s) {
     if (!s || beam < 0 || (!s->cfg.mock && !src)) return RFIM_ERR_INVALID_ARG;
     s->st.submitted++;
     auto it = s->in_flight.find(beam);
@@ -277,6 +280,12 @@ rfim_status rfim_serve_submit(rfim_serve* s, int32_t beam, const void* src, int3
     }
     const int slot = s->free_slots.back();
     if (!s->cfg.mock) {
+        if (!src_on_host && src_stream) {
+            // the copy waits for the work the caller queued on src's stream
+            if (hipEventRecord(s->src_ready, (hipStream_t)src_stream) != hipSuccess ||
+                hipStreamWaitEvent(s->stream, s->src_ready, 0) != hipSuccess)
+                return RFIM_ERR_DEVICE;
+        }
         const hipMemcpyKind kind = src_on_host ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
         if (hipMemcpyAsync(s->pool + (size_t)slot * s->bytes, src, s->bytes, kind, s->stream) != hipSuccess)
             return RFIM_ERR_DEVICE;

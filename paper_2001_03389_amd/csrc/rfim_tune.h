@@ -5,6 +5,7 @@
 #pragma once
 
 #include <string>
+#include <vector>
 
 #include "rfim_internal.h"
 
@@ -31,11 +32,17 @@ std::string tune_key(const rfim_beam* shapes, int32_t nbeams, const rfim_step* s
 rfim_status tune_cache_lookup(const char* path, const rfim_beam* shapes, int32_t nbeams,
                               const rfim_step* steps, int32_t nsteps, TuneParams* out);
 
+// One timed candidate of a tuning run.
+struct TuneRow {
+    TuneParams p;
+    double ms;
+};
+
 // Adds or replaces the key's entry (the file is rewritten through a
-// temporary and a rename).
+// temporary and a rename); `table` (may be empty) is recorded with it.
 rfim_status tune_cache_store(const char* path, const rfim_beam* shapes, int32_t nbeams,
                              const rfim_step* steps, int32_t nsteps, const TuneParams& p, double ms,
-                             int candidates);
+                             const std::vector<TuneRow>& table);
 
 // Host helpers defined in rfim_api.hip.
 KExact make_k(double k);

@@ -2,17 +2,19 @@
 // parameters are tuned per setup and platform, and the configurations found
 // are saved for production runs).
 //
-// rfim_autotune allocates beams of the requested shapes, fills them with a
-// deterministic pseudo-random pattern on the device, and times every
-// candidate configuration with HIP events.  A candidate is admissible only if
-// its outputs and flags are bit-identical to the default configuration's
-// (the cuts are exact, so every launch shape must agree).  The fastest
-// admissible candidate is written to the JSON cache file under a key made of
-// the beam shapes and the step list; rfim_plan_create reads it back.
+// rfim_autotune allocates beams of the requested shapes, fills them on the
+// device with a deterministic pattern shaped like channelised telescope data,
+// and times every candidate configuration with HIP events.  Every candidate's
+// outputs and flags must be bit-identical to the default configuration's (the
+// cuts are exact, so every launch shape must agree): a difference is a defect
+// and fails the call.  The fastest candidate is written to the JSON cache
+// file under a key made of the beam shapes and the step list, with the table
+// of all candidates' times; rfim_plan_create reads it back.
 //
 // Cache file: one JSON object; each entry sits on its own line,
 //   "<key>": {"u8_tile_cap": 64, "f32_lds": 81920, "f32_tile_cap": 64, "u8_lds": 51200, "ms": 1.5,
-//             "candidates": 9}
+//             "candidates": 9, "table": [[64, 51200, 81920, 64, 1.5], ...]}
+// (table rows: u8 tile cap, u8 LDS, f32 LDS, f32 tile cap, ms per run)
 #include <algorithm>
 #include <cstdio>
 #include <cstdlib>
@@ -117,7 +119,7 @@ rfim_status tune_cache_lookup(const char* path, const rfim_beam* shapes, int32_t
 
 rfim_status tune_cache_store(const char* path, const rfim_beam* shapes, int32_t nbeams,
                              const rfim_step* steps, int32_t nsteps, const TuneParams& p, double ms,
-                             int candidates) {
+                             const std::vector<TuneRow>& table) {
     bool exists = false;
     const std::vector<std::string> lines = read_lines(path, &exists);
     const std::string pre = entry_prefix(tune_key(shapes, nbeams, steps, nsteps));
@@ -132,9 +134,18 @@ rfim_status tune_cache_store(const char* path, const rfim_beam* shapes, int32_t 
     char buf[256];
     std::snprintf(buf, sizeof buf,
                   "\"u8_tile_cap\": %d, \"f32_lds\": %zu, \"f32_tile_cap\": %d, \"u8_lds\": %zu, \"ms\": %.6f, "
-                  "\"candidates\": %d}",
-                  p.u8_tile_cap, p.f32_lds, p.f32_tile_cap, p.u8_lds, ms, candidates);
-    entries.push_back(pre + buf);
+                  "\"candidates\": %zu, \"table\": [",
+                  p.u8_tile_cap, p.f32_lds, p.f32_tile_cap, p.u8_lds, ms, table.size());
+    std::string e = pre + buf;
+    // table rows: [u8 tile cap, u8 LDS, f32 LDS, f32 tile cap, ms per run]
+    for (size_t i = 0; i < table.size(); i++) {
+        const TuneRow& r = table[i];
+        std::snprintf(buf, sizeof buf, "%s[%d, %zu, %zu, %d, %.6f]", i ? ", " : "", r.p.u8_tile_cap, r.p.u8_lds,
+                      r.p.f32_lds, r.p.f32_tile_cap, r.ms);
+        e += buf;
+    }
+    e += "]}";
+    entries.push_back(e);
     const std::string tmp = std::string(path) + ".tmp";
     {
         std::ofstream f(tmp, std::ios::trunc);
@@ -161,32 +172,47 @@ __device__ inline uint32_t mix32(uint64_t x) {
     return (uint32_t)x;
 }
 
-// deterministic test pattern: uint8 around a per-row level with rare spikes,
-// float32 a sum of uniforms (roughly normal) with rare large values
+// Deterministic test pattern shaped like channelised telescope data: per
+// channel a level and a spread (uint8: level 60..100, spread 6..12; float32:
+// level 0, spread 1), approximately normal noise (a sum of four uniforms),
+// about 1.3 % of channels carrying persistent narrow-band interference of
+// 5..20 spreads, and broadband impulses of 8 spreads in all channels at about
+// 0.24 % of the time samples.  Samples past T in a row are zero.
 __global__ void k_fill(void* p, int dtype, int64_t rows, int64_t stride, int64_t T, uint64_t seed) {
     const int64_t n = rows * stride;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         const int64_t r = i / stride, t = i - r * stride;
         const uint32_t h = mix32(seed * 0x9E3779B97F4A7C15ull + (uint64_t)i);
+        const uint32_t h2 = mix32((seed + 0x5851F42Dull) * 0xD1B54A32D192ED03ull + (uint64_t)i);
         const uint32_t hr = mix32(seed ^ (0xABCDull + (uint64_t)r * 77));
-        const bool spike = (h & 1023u) == 0;
+        const uint32_t ht = mix32((seed << 20) ^ (0x1234567ull + (uint64_t)t * 131));
+        const float u = ((float)(h & 0xFFFFu) + (float)(h >> 16) + (float)(h2 & 0xFFFFu) + (float)(h2 >> 16)) *
+                        (1.0f / 65536.0f);
+        float z = (u - 2.0f) * 1.7320508f;   // mean 0, variance 1
+        if (((hr >> 16) % 77u) == 0u) z += 5.0f + (float)((hr >> 24) & 15u);
+        if ((ht % 417u) == 0u) z += 8.0f;
         if (dtype == RFIM_U8) {
-            int v = 60 + (int)(hr % 40) + (int)((h >> 10) & 15) + (int)((h >> 14) & 15) - 15;
-            if (spike) v += 100;
-            ((uint8_t*)p)[i] = (uint8_t)(t < T ? (v < 0 ? 0 : (v > 255 ? 255 : v)) : 0);
+            const float level = 60.0f + (float)(hr % 41u), spread = 6.0f + (float)((hr >> 8) % 7u);
+            float v = rintf(level + spread * z);
+            v = v < 0.0f ? 0.0f : (v > 255.0f ? 255.0f : v);
+            ((uint8_t*)p)[i] = (uint8_t)(t < T ? (int)v : 0);
         } else {
-            float v = ((float)((h >> 8) & 255u) + (float)((h >> 16) & 255u) + (float)(h >> 24) - 382.5f) / 128.0f;
-            if (spike) v += 12.0f;
-            ((float*)p)[i] = t < T ? v : 0.0f;
+            ((float*)p)[i] = t < T ? z : 0.0f;
         }
     }
 }
 
-// number of differing bytes between a and b
-__global__ void k_count_diff(const uint8_t* a, const uint8_t* b, int64_t n, unsigned long long* out) {
+// number of differing bytes between a and b over bytes [0, row_bytes) of
+// each of `rows` rows `pitch` bytes apart (padding past nsamp is never
+// written by the kernels and is not compared)
+__global__ void k_count_diff(const uint8_t* a, const uint8_t* b, int64_t rows, int64_t pitch, int64_t row_bytes,
+                             unsigned long long* out) {
     unsigned long long c = 0;
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        c += a[i] != b[i];
+    const int64_t n = rows * row_bytes;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t r = i / row_bytes, t = i - r * row_bytes;
+        c += a[r * pitch + t] != b[r * pitch + t];
+    }
     if (c) atomicAdd(out, c);
 }
 
@@ -241,7 +267,7 @@ rfim_status rfim_tune_store(const char* path, const rfim_beam* shapes, int32_t n
     if (p.u8_tile_cap < 4 || p.u8_tile_cap > 64 || p.f32_lds < 1024 || p.f32_lds > (1u << 20) ||
         p.f32_tile_cap < 4 || p.f32_tile_cap > 64 || p.u8_lds < 4096 || p.u8_lds > (1u << 20))
         return RFIM_ERR_INVALID_ARG;
-    return tune_cache_store(path, shapes, nbeams, steps, nsteps, p, ms, 0);
+    return tune_cache_store(path, shapes, nbeams, steps, nsteps, p, ms, {});
 }
 
 rfim_status rfim_autotune(const rfim_beam* shapes, int32_t nbeams, const rfim_step* steps, int32_t nsteps,
@@ -317,45 +343,60 @@ rfim_status rfim_autotune(const rfim_beam* shapes, int32_t nbeams, const rfim_st
                 }
 
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    (void)hipEventCreate(&e0);
-    (void)hipEventCreate(&e1);
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) st = RFIM_ERR_DEVICE;
     double best = 1e30;
     TuneParams bestp = def;
-    int tried = 0;
+    std::vector<TuneRow> table;
     const int reps = 5;
     for (size_t ci = 0; ci < cands.size() && st == RFIM_OK; ci++) {
         rfim_plan* plan = nullptr;
-        if (plan_create_tuned(shapes, nbeams, steps, nsteps, cands[ci], &plan) != RFIM_OK) continue;
+        const rfim_status pc = plan_create_tuned(shapes, nbeams, steps, nsteps, cands[ci], &plan);
+        if (pc != RFIM_OK) {
+            // a candidate whose tiles do not fit this device is not applicable;
+            // the default must always be
+            if (ci == 0 || pc != RFIM_ERR_UNSUPPORTED) st = pc;
+            continue;
+        }
         const std::vector<rfim_beam> bv = beams_to(ci == 0);
-        rfim_status rs = rfim_pipeline_run(bv.data(), nbeams, steps, nsteps, plan, stream);   // warm-up
-        bool ok = rs == RFIM_OK;
-        if (ok && ci > 0) {
-            // bit-identical to the default configuration, or rejected
-            if (hipMemsetAsync(d_diff, 0, sizeof(unsigned long long), s) != hipSuccess) ok = false;
-            for (int i = 0; i < nbeams && ok; i++) {
+        st = rfim_pipeline_run(bv.data(), nbeams, steps, nsteps, plan, stream);   // warm-up (the reference for ci 0)
+        if (st == RFIM_OK && ci > 0) {
+            // bit-identical to the default configuration over [0, nsamp) of every row
+            if (hipMemsetAsync(d_diff, 0, sizeof(unsigned long long), s) != hipSuccess) st = RFIM_ERR_DEVICE;
+            for (int i = 0; i < nbeams && st == RFIM_OK; i++) {
+                const rfim_beam& b = shapes[i];
+                const int64_t es = (int64_t)elem_size(b.dtype);
                 hipLaunchKernelGGL(k_count_diff, dim3(1024), dim3(256), 0, s, (const uint8_t*)tb[i].out,
-                                   (const uint8_t*)tb[i].ref, (int64_t)tb[i].bytes, d_diff);
+                                   (const uint8_t*)tb[i].ref, b.nchan, b.row_stride * es, b.nsamp * es, d_diff);
                 if (tb[i].fbytes)
                     hipLaunchKernelGGL(k_count_diff, dim3(1024), dim3(256), 0, s, (const uint8_t*)tb[i].fl,
-                                       (const uint8_t*)tb[i].fref, (int64_t)tb[i].fbytes, d_diff);
+                                       (const uint8_t*)tb[i].fref, b.nchan, b.row_stride, b.nsamp, d_diff);
+                if (hipGetLastError() != hipSuccess) st = RFIM_ERR_DEVICE;
             }
-            unsigned long long diff = 1;
-            if (ok && hipMemcpyAsync(&diff, d_diff, sizeof diff, hipMemcpyDeviceToHost, s) == hipSuccess &&
-                hipStreamSynchronize(s) == hipSuccess)
-                ok = diff == 0;
-            else
-                ok = false;
-            if (!ok) std::fprintf(stderr, "rfim_autotune: candidate %zu differs from the default, rejected\n", ci);
+            unsigned long long diff = 0;
+            if (st == RFIM_OK &&
+                (hipMemcpyAsync(&diff, d_diff, sizeof diff, hipMemcpyDeviceToHost, s) != hipSuccess ||
+                 hipStreamSynchronize(s) != hipSuccess))
+                st = RFIM_ERR_DEVICE;
+            if (st == RFIM_OK && diff != 0) {
+                std::fprintf(stderr,
+                             "rfim_autotune: candidate %zu (u8 tile cap %d, u8 LDS %zu, f32 LDS %zu, f32 tile cap %d) "
+                             "differs from the default configuration in %llu bytes\n",
+                             ci, cands[ci].u8_tile_cap, cands[ci].u8_lds, cands[ci].f32_lds, cands[ci].f32_tile_cap,
+                             diff);
+                st = RFIM_ERR_MISMATCH;
+            }
         }
-        if (ok) {
-            (void)hipEventRecord(e0, s);
-            for (int r = 0; r < reps && ok; r++)
-                ok = rfim_pipeline_run(bv.data(), nbeams, steps, nsteps, plan, stream) == RFIM_OK;
-            (void)hipEventRecord(e1, s);
+        if (st == RFIM_OK) {
+            if (hipEventRecord(e0, s) != hipSuccess) st = RFIM_ERR_DEVICE;
+            for (int r = 0; r < reps && st == RFIM_OK; r++)
+                st = rfim_pipeline_run(bv.data(), nbeams, steps, nsteps, plan, stream);
             float ms = 0.f;
-            if (ok && hipEventSynchronize(e1) == hipSuccess && hipEventElapsedTime(&ms, e0, e1) == hipSuccess) {
-                tried++;
+            if (st == RFIM_OK && (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                                  hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+                st = RFIM_ERR_DEVICE;
+            if (st == RFIM_OK) {
                 const double per = ms / reps;
+                table.push_back({cands[ci], per});
                 if (per < best) {
                     best = per;
                     bestp = cands[ci];
@@ -363,7 +404,6 @@ rfim_status rfim_autotune(const rfim_beam* shapes, int32_t nbeams, const rfim_st
             }
         }
         (void)rfim_plan_destroy(plan);
-        if (ci == 0 && !ok) st = RFIM_ERR_DEVICE;   // the default must run
     }
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
@@ -372,7 +412,7 @@ rfim_status rfim_autotune(const rfim_beam* shapes, int32_t nbeams, const rfim_st
     (void)hipFree(d_diff);
     if (st != RFIM_OK) return st;
     if (best_ms) *best_ms = best;
-    return tune_cache_store(tune_cache_path, shapes, nbeams, steps, nsteps, bestp, best, tried);
+    return tune_cache_store(tune_cache_path, shapes, nbeams, steps, nsteps, bestp, best, table);
 }
 
 }  // extern "C"

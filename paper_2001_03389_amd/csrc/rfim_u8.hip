@@ -258,109 +258,112 @@ __global__ __launch_bounds__(kBlock) void k_td_rows_u8(const DevBeam* __restrict
         s_r_all[kRowsPerWG][kMaxSteps];
     __shared__ unsigned long long s_mv_all[kRowsPerWG][kMaxSteps];
 
+    __shared__ int s_beam[kRowsPerWG];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int64_t g = (int64_t)blockIdx.x * kRowsPerWG + wave;
-    if (g >= total_rows) return;
-    unsigned long long* s_mv = s_mv_all[wave];
-    uint32_t* hist = hist_all[wave];
-    int* s_lo = s_lo_all[wave];
-    int* s_hi = s_hi_all[wave];
-    int* s_r = s_r_all[wave];
-    const int b = find_beam_by_row(beams, nbeams, g);
-    const DevBeam& bm = beams[b];
-    const int64_t c = g - bm.row0;
-    const int64_t T = bm.T;
-    const uint64_t n = (uint64_t)T;
-    const uint8_t* row = (const uint8_t*)bm.in + c * bm.stride;
-    uint32_t* h = hist + (lane & (kHistCopies - 1)) * kHistPitch;
+    // waves past the last row skip the row work but still reach the
+    // work-group barrier of the flag counts below
+    if (g < total_rows) {
+        unsigned long long* s_mv = s_mv_all[wave];
+        uint32_t* hist = hist_all[wave];
+        int* s_lo = s_lo_all[wave];
+        int* s_hi = s_hi_all[wave];
+        int* s_r = s_r_all[wave];
+        const int b = find_beam_by_row(beams, nbeams, g);
+        const DevBeam& bm = beams[b];
+        const int64_t c = g - bm.row0;
+        const int64_t T = bm.T;
+        const uint64_t n = (uint64_t)T;
+        const uint8_t* row = (const uint8_t*)bm.in + c * bm.stride;
+        uint32_t* h = hist + (lane & (kHistCopies - 1)) * kHistPitch;
 
-    auto clear_hist = [&] {
-        for (int i = lane; i < kHistCopies * kHistPitch; i += 64) hist[i] = 0;
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-    };
-    // lane l owns the byte values 4l .. 4l+3
-    auto read_hist = [&](uint32_t hv[4]) {
+        auto clear_hist = [&] {
+            for (int i = lane; i < kHistCopies * kHistPitch; i += 64) hist[i] = 0;
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+        };
+        // lane l owns the byte values 4l .. 4l+3
+        auto read_hist = [&](uint32_t hv[4]) {
+            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+#pragma unroll
+            for (int u = 0; u < 4; u++) {
+                uint32_t t = 0;
+#pragma unroll
+                for (int cp = 0; cp < kHistCopies; cp++) t += hist[cp * kHistPitch + 4 * lane + u];
+                hv[u] = t;
+            }
+        };
+
+        // Measured alternatives, all slower than one pass with a full histogram:
+        // exact S1, S2 by dot4 with a histogram of only the bytes outside a band
+        // around the row's bulk (a band from the row's first 2 KB; a band from the
+        // first cut in a second pass; or the row held in VGPRs with the dwords
+        // holding out-of-band bytes compacted into an LDS queue first).  The
+        // first two leave some out-of-band byte in nearly every wave-wide dword;
+        // the last costs more occupancy than the atomics it saves.
+        {
+            // every value tracked: the row's full histogram
+            clear_hist();
+            row_pass(row, T, lane, [&](uint32_t x) { hist4(h, x); }, [&](uint32_t x) { atomicAdd(&h[x], 1u); });
+            uint32_t hv[4];
+            read_hist(hv);
+            td_decide(seg, n, hv, 0, 0, 0, 1, 0, lane, s_lo, s_hi, s_r, s_mv);
+        }
         __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
         __builtin_amdgcn_wave_barrier();
-#pragma unroll
-        for (int u = 0; u < 4; u++) {
-            uint32_t t = 0;
-#pragma unroll
-            for (int cp = 0; cp < kHistCopies; cp++) t += hist[cp * kHistPitch + 4 * lane + u];
-            hv[u] = t;
-        }
-    };
 
-    // Measured alternatives, all slower than one pass with a full histogram:
-    // exact S1, S2 by dot4 with a histogram of only the bytes outside a band
-    // around the row's bulk (a band from the row's first 2 KB; a band from the
-    // first cut in a second pass; or the row held in VGPRs with the dwords
-    // holding out-of-band bytes compacted into an LDS queue first).  The
-    // first two leave some out-of-band byte in nearly every wave-wide dword;
-    // the last costs more occupancy than the atomics it saves.
-    {
-        // every value tracked: the row's full histogram
-        clear_hist();
-        row_pass(row, T, lane, [&](uint32_t x) { hist4(h, x); }, [&](uint32_t x) { atomicAdd(&h[x], 1u); });
-        uint32_t hv[4];
-        read_hist(hv);
-        td_decide(seg, n, hv, 0, 0, 0, 1, 0, lane, s_lo, s_hi, s_r, s_mv);
-    }
-    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-
-    // composite record of the run, one u32 per step:
-    //   [7:0] L_j, [15:8] H_j  -- nested interval: a sample stays untouched
-    //                             through step j iff L_j <= x <= H_j
-    //   [23:16] value a sample first cut at step j ends with
-    //   [31:24] flag bits it collects (step j and any later step that cuts
-    //           the replacement value)
-    if (lane < seg.n_td) {
-        const int j = lane;
-        int L = 0, H = 255;
-        for (int k = 0; k <= j; k++) {
-            L = max(L, s_lo[k]);
-            H = min(H, s_hi[k]);
-        }
-        int val = s_r[j];
-        uint32_t f = seg.td[j].bit >= 0 ? (1u << seg.td[j].bit) : 0u;
-        for (int k = j + 1; k < seg.n_td; k++) {
-            if (val < s_lo[k] || val > s_hi[k]) {
-                val = s_r[k];
-                if (seg.td[k].bit >= 0) f |= 1u << seg.td[k].bit;
+        // composite record of the run, one u32 per step:
+        //   [7:0] L_j, [15:8] H_j  -- nested interval: a sample stays untouched
+        //                             through step j iff L_j <= x <= H_j
+        //   [23:16] value a sample first cut at step j ends with
+        //   [31:24] flag bits it collects (step j and any later step that cuts
+        //           the replacement value)
+        if (lane < seg.n_td) {
+            const int j = lane;
+            int L = 0, H = 255;
+            for (int k = 0; k <= j; k++) {
+                L = max(L, s_lo[k]);
+                H = min(H, s_hi[k]);
             }
+            int val = s_r[j];
+            uint32_t f = seg.td[j].bit >= 0 ? (1u << seg.td[j].bit) : 0u;
+            for (int k = j + 1; k < seg.n_td; k++) {
+                if (val < s_lo[k] || val > s_hi[k]) {
+                    val = s_r[k];
+                    if (seg.td[k].bit >= 0) f |= 1u << seg.td[k].bit;
+                }
+            }
+            if (L > H) {  // empty interval: every value is cut
+                L = 1;
+                H = 0;
+            }
+            rec[g * seg.n_td + j] = (uint32_t)L | ((uint32_t)H << 8) | ((uint32_t)val << 16) | (f << 24);
         }
-        if (L > H) {  // empty interval: every value is cut
-            L = 1;
-            H = 0;
-        }
-        rec[g * seg.n_td + j] = (uint32_t)L | ((uint32_t)H << 8) | ((uint32_t)val << 16) | (f << 24);
-    }
+        if (lane == 0) s_beam[wave] = bm.cidx;
+    }   // g < total_rows
 
     // Flag counts.  Every row of a beam adds to the same few counters, and
     // one atomic per row and step left the kernel waiting on those atomics
     // for most of its time; so the work-group's rows are summed in LDS first
     // and each step's sum goes out with one atomic per beam.
     if (counts) {
-        __shared__ int s_beam[kRowsPerWG];
-        if (lane == 0) s_beam[wave] = bm.cidx;
-        __syncthreads();   // waves past the last row have left; they are not waited for
+        __syncthreads();
         const int j = threadIdx.x;
-        if (j < seg.n_td && seg.td[j].bit >= 0) {
+        if (j < seg.n_td) {
             const int64_t g0 = (int64_t)blockIdx.x * kRowsPerWG;
             const int nw = (int)min((int64_t)kRowsPerWG, total_rows - g0);
             int cb = s_beam[0];
             unsigned long long sum = 0;
             for (int w = 0; w < nw; w++) {
                 if (s_beam[w] != cb) {
-                    if (sum) atomicAdd(&counts[(int64_t)cb * count_stride + seg.td[j].bit], sum);
+                    if (sum) atomicAdd(&counts[(int64_t)cb * count_stride + seg.td[j].ci], sum);
                     cb = s_beam[w];
                     sum = 0;
                 }
                 sum += s_mv_all[w][j];
             }
-            if (sum) atomicAdd(&counts[(int64_t)cb * count_stride + seg.td[j].bit], sum);
+            if (sum) atomicAdd(&counts[(int64_t)cb * count_stride + seg.td[j].ci], sum);
         }
     }
 }
@@ -863,7 +866,7 @@ __device__ inline void fd_steps(const TileCtx& k, const Segment& seg, uint8_t* t
                 }
             }
         }
-        if (count && st.bit >= 0) {   // one LDS add per wave (all lanes are here)
+        if (count) {   // one LDS add per wave (all lanes are here)
             const uint64_t tot = wave_sum_u64_split(valid ? nflag : 0u);
             if ((tid & 63) == 0 && tot) atomicAdd(&s_cnt[s], (unsigned long long)tot);
         }
@@ -881,7 +884,6 @@ __device__ inline uint32_t group_sum_dpp(uint32_t v) {
     return v;
 }
 
-constexpr int kB32MaxBins = 7;   // bins per lane in the 32-channel path (LDS budget bound)
 
 // kept byte values of a 32-channel bin with sum S under the cut |32 x - S| <= z:
 // ceil((S - z)/32) <= x <= floor((S + z)/32), as outside_mask constants
@@ -1078,7 +1080,7 @@ __device__ inline void fd_steps_b32(const TileCtx& k, const Segment& seg, uint8_
                 nflag += bin32_replace(tile, ftile, off, a, b, m, lower_median32(a, b), fbit, want_flags);
             }
         }
-        if (count && st.bit >= 0) {   // one LDS add per wave (all lanes are here)
+        if (count) {   // one LDS add per wave (all lanes are here)
             const uint32_t tot = wave_sum_u32(valid ? nflag : 0u);
             if ((tid & 63) == 0 && tot) atomicAdd(&s_cnt[s], (unsigned long long)tot);
         }
@@ -1103,7 +1105,7 @@ __device__ inline void fd_steps_b32(const TileCtx& k, const Segment& seg, uint8_
                 const uint32_t n = bin32_replace(tile, ftile, off, a, b, m, lower_median32(a, b), fbit, want_flags);
                 if (k.t0 + (int64_t)tl2 < k.T) nlist += n;
             }
-            if (count && st.bit >= 0) {   // one LDS add per wave
+            if (count) {   // one LDS add per wave
                 const uint32_t tot = wave_sum_u32(nlist);
                 if (lane == 0 && tot) atomicAdd(&s_cnt[s], (unsigned long long)tot);
             }
@@ -1267,15 +1269,13 @@ __global__ __launch_bounds__(kBlock) void k_fused_u8(const DevBeam* __restrict__
 
     // ---- phase 2: FD steps
     if (seg.n_fd > 0) {
-        // 32-channel bins with every lane's bins whole: the specialised path
-        bool b32 = VEC && (k.C & 31) == 0 && (k.C >> 5) <= kB32MaxBins * (kBlock / k.Tt);
-        for (int s = 0; s < seg.n_fd; s++) b32 &= seg.fd[s].bin == 32 || (seg.fd[s].bin == 0 && k.C == 32);
+        // the host chose the path for this beam's shape, tile and bins
         const bool cnt = counts != nullptr;
-        if (b32 && k.Tt == 32)
+        if (VEC && bm.path == RFIM_FD_PATH_U8_BIN32_G8)
             fd_steps_b32<8>(k, seg, tile, ftile, want_flags, cnt, s_cnt, exc_pos, &exc_n, kExcCap, s_z);
-        else if (b32 && k.Tt == 16)
+        else if (VEC && bm.path == RFIM_FD_PATH_U8_BIN32_G16)
             fd_steps_b32<16>(k, seg, tile, ftile, want_flags, cnt, s_cnt, exc_pos, &exc_n, kExcCap, s_z);
-        else if (b32 && k.Tt == 64)
+        else if (VEC && bm.path == RFIM_FD_PATH_U8_BIN32_G4)
             fd_steps_b32<4>(k, seg, tile, ftile, want_flags, cnt, s_cnt, exc_pos, &exc_n, kExcCap, s_z);
         else
             fd_steps<VEC>(k, seg, tile, ftile, want_flags, cnt, s_cnt);
@@ -1290,8 +1290,8 @@ __global__ __launch_bounds__(kBlock) void k_fused_u8(const DevBeam* __restrict__
     } else {
         for (int64_t idx = tid; idx < ntask; idx += kBlock) tile_store_task<false>(k, idx, tile, ftile, want_flags);
     }
-    if (counts && seg.n_fd > 0 && tid < seg.n_fd && s_cnt[tid] && seg.fd[tid].bit >= 0)
-        atomicAdd(&counts[(int64_t)bm.cidx * count_stride + seg.fd[tid].bit], s_cnt[tid]);
+    if (counts && seg.n_fd > 0 && tid < seg.n_fd && s_cnt[tid])
+        atomicAdd(&counts[(int64_t)bm.cidx * count_stride + seg.fd[tid].ci], s_cnt[tid]);
 }
 
 hipError_t launch_td_rows_u8(const DevBeam* d_beams, int nbeams, int64_t total_rows,

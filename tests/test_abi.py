@@ -80,3 +80,4 @@ def test_plan_create_rejects_bad_shapes():
     h = ctypes.c_void_p()
     assert rf.lib().rfim_plan_create(arr, 1, st, 1, None, ctypes.byref(h)) == rf.RFIM_ERR_INVALID_ARG
     assert not h.value
+

@@ -1,7 +1,8 @@
 """GPU: the HIP-graph form of a plan and the auto-tuner.  A captured graph
 is replayed several times with eager work and synchronisation in between;
-every replay must give the eager run's bytes and flag counts.  The auto-tuner
-writes a cache entry whose plan gives the default plan's bytes."""
+every replay must give the oracle's bytes, flags and flag counts, as must a
+graph replayed on other buffers and the plan the auto-tuner's cache entry
+selects."""
 from __future__ import annotations
 
 import sys
@@ -9,6 +10,7 @@ import sys
 import numpy as np
 import pytest
 
+import oracle
 import synth
 
 pytestmark = pytest.mark.gpu
@@ -39,6 +41,12 @@ def mixed_beams():
 STEPS = [synth.td(3.5), synth.td(3.0, "median"), synth.fd(2.75, 32), synth.fd(2.5, 32, "median")]
 
 
+def oracle_refs(host):
+    refs = [oracle.pipeline(h, STEPS, want_flags=True) for h in host]
+    counts = [[int(((f >> j) & 1).sum()) for j in range(len(STEPS))] for _, f in refs]
+    return [o.view(np.uint8) for o, _ in refs], [f for _, f in refs], counts
+
+
 def test_graph_replays_match_eager(rf):
     import torch
     dev = torch.device("cuda:0")
@@ -46,12 +54,14 @@ def test_graph_replays_match_eager(rf):
     ins = [torch.from_numpy(h).to(dev) for h in host]
     outs_e = [torch.empty_like(x) for x in ins]
     fl_e = [torch.zeros(x.shape, dtype=torch.uint8, device=dev) for x in ins]
+    want, want_f, want_counts = oracle_refs(host)
     pe = rf.Plan(ins, STEPS, outputs=outs_e, flags=fl_e)
     rf.rfim_pipeline_run(ins, STEPS, outputs=outs_e, flags=fl_e, plan=pe)
     torch.cuda.synchronize()
-    want_counts = pe.flag_counts()
-    want = [o.cpu().numpy().view(np.uint8).copy() for o in outs_e]
-    want_f = [f.cpu().numpy().copy() for f in fl_e]
+    assert pe.flag_counts() == want_counts
+    for i in range(len(host)):
+        np.testing.assert_array_equal(outs_e[i].cpu().numpy().view(np.uint8), want[i], err_msg=f"eager beam {i}")
+        np.testing.assert_array_equal(fl_e[i].cpu().numpy(), want_f[i], err_msg=f"eager beam {i} flags")
     pe.close()
 
     outs = [torch.empty_like(x) for x in ins]
@@ -90,9 +100,7 @@ def test_graph_replay_on_other_buffers(rf):
     ins_b = [torch.from_numpy(h).to(dev) for h in host_b]
     outs_a = [torch.empty_like(x) for x in ins_a]
     outs_b = [torch.empty_like(x) for x in ins_b]
-    want_b = [torch.empty_like(x) for x in ins_b]
-    rf.rfim_pipeline_run(ins_b, STEPS, outputs=want_b)
-    torch.cuda.synchronize()
+    want_b, _, _ = oracle_refs(host_b)
     p = rf.Plan(ins_a, STEPS, outputs=outs_a)
     stream = torch.cuda.Stream()
     p.capture(ins_a, outputs=outs_a, stream=stream)
@@ -104,7 +112,8 @@ def test_graph_replay_on_other_buffers(rf):
         p.replay_on(ins_b, outputs=outs_b, stream=stream)
         stream.synchronize()
         for i in range(len(host_b)):
-            assert torch.equal(outs_b[i], want_b[i]), f"replay {rep} beam {i}"
+            np.testing.assert_array_equal(outs_b[i].cpu().numpy().view(np.uint8), want_b[i],
+                                          err_msg=f"replay {rep} beam {i}")
     wrong = [torch.empty((x.shape[0], x.shape[1] - 4), dtype=x.dtype, device=dev) for x in ins_b]
     with pytest.raises(rf.RfimError):
         p.replay_on(wrong, outputs=[torch.empty_like(w) for w in wrong], stream=stream)
@@ -124,13 +133,17 @@ def test_autotune_cache_gives_identical_plan(rf, tmp_path):
     params = rf.tune_lookup(cache, shapes, STEPS)
     assert params is not None
     say(f"tuned {params} {ms:.3f} ms")
-    res = []
+    want, _, want_counts = oracle_refs(host)
     for tc in (None, cache):
         outs = [torch.empty_like(x) for x in ins]
         p = rf.Plan(ins, STEPS, outputs=outs, tune_cache=tc)
         rf.rfim_pipeline_run(ins, STEPS, outputs=outs, plan=p)
         torch.cuda.synchronize()
-        res.append([o.cpu().numpy().view(np.uint8) for o in outs])
+        for i, o in enumerate(outs):
+            np.testing.assert_array_equal(o.cpu().numpy().view(np.uint8), want[i], err_msg=f"tune={tc} beam {i}")
+        assert p.flag_counts() == want_counts
         p.close()
-    for a, b in zip(*res):
-        np.testing.assert_array_equal(a, b)
+    # the cache entry records every candidate's time
+    import json
+    entry = next(iter(json.load(open(cache)).values()))
+    assert entry["candidates"] == len(entry["table"]) > 1

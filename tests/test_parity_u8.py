@@ -268,3 +268,35 @@ def test_interleaved_step_list(rf):
     check_against_oracle([x], steps, out, fl)
     out2, _, _ = gpu_run(rf, [x], steps, flags=False)
     np.testing.assert_array_equal(out2[0], out[0])
+
+
+def test_flag_counts_beyond_eight_steps(rf):
+    """Per-step flag counts of a 12-step list (no flag array: bits stop at 8
+    steps, counts do not) on a uint8 and a float32 beam in one call.  The
+    oracle runs the list one step at a time, each step on the previous one's
+    output, which is the pipeline's definition."""
+    import torch
+    rng = np.random.default_rng(12)
+    xu = rng.normal(90, 12, size=(96, 1500)).clip(0, 255).astype(np.uint8)
+    xu[7, :] = 250
+    xu[:, 400:402] = 255
+    xf = rng.standard_normal((64, 2000)).astype(np.float32)
+    xf[3] += 7.0
+    steps = [synth.td(2.5), synth.fd(2.25, 16), synth.td(2.0, "median"), synth.fd(2.0, 32, "median"),
+             synth.td(1.75), synth.td(1.5, "median"), synth.fd(1.75, 8), synth.fd(1.5, 0),
+             synth.td(1.25), synth.fd(1.25, 16, "median"), synth.td(1.0), synth.fd(1.0, 32)]
+    dev = torch.device("cuda:0")
+    ins = [torch.from_numpy(xu).to(dev), torch.from_numpy(xf).to(dev)]
+    outs = [torch.empty_like(x) for x in ins]
+    p = rf.Plan(ins, steps, outputs=outs)
+    rf.rfim_pipeline_run(ins, steps, outputs=outs, plan=p)
+    torch.cuda.synchronize()
+    counts = p.flag_counts()
+    p.close()
+    for b, x in enumerate((xu, xf)):
+        cur, want = x, []
+        for st in steps:
+            cur, f = oracle.pipeline(cur, [st], want_flags=True)
+            want.append(int((f & 1).sum()))
+        np.testing.assert_array_equal(outs[b].cpu().numpy().view(np.uint8), cur.view(np.uint8))
+        assert counts[b] == want, (b, counts[b], want)

@@ -130,3 +130,17 @@ def test_poisson_load_sustained_or_backlogged(beams, ok):
         assert st["p99_s"] < 0.1 and st["deadline_misses"] == 0
     else:
         assert st["rejected_budget"] > 0 or st["deadline_misses"] > 0
+
+
+def test_submit_checks_batch_tensors():
+    """The binding refuses a batch of the wrong size, dtype or layout before
+    anything is copied (the C side copies nchan * nsamp elements)."""
+    import torch
+    s = mock(nchan=32, nsamp=8, hbm_budget=64 * 256)
+    for bad in (torch.zeros(31, 8, dtype=torch.uint8), torch.zeros(32, 8, dtype=torch.float32),
+                torch.zeros(8, 32, dtype=torch.uint8).t()):
+        with pytest.raises(ValueError):
+            s.submit(0, bad, arrival_s=0.0)
+    with pytest.raises(ValueError):   # dst must be a device tensor
+        s.submit(0, arrival_s=0.0, dst=torch.zeros(32, 8, dtype=torch.uint8))
+    s.close()
