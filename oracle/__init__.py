@@ -1,7 +1,8 @@
-"""Test-only oracle for the RFIm sigma cuts (arXiv:2001.03389, Section IV).
+"""Test-only oracle for the RFIm sigma cuts (arXiv:2001.03389, Section IV)
+and for the dedispersion search stage that follows them (Eq. 2).
 
-Plain single-threaded exact C implementation (``rfim_oracle.c``) behind a
-ctypes wrapper.  This package is test infrastructure: only the tests, the
+Plain single-threaded C implementations (``rfim_oracle.c``, exact;
+``dedisp_oracle.c``) behind a ctypes wrapper.  This package is test infrastructure: only the tests, the
 smoke check and the benchmark's CPU-baseline leg may import it.  It shares no
 code with the GPU library.
 """
@@ -48,6 +49,12 @@ def _load():
         lib.oracle_mean_f32.restype = ctypes.c_float
         lib.oracle_mean_u8.argtypes = [vp, i64]
         lib.oracle_mean_u8.restype = ctypes.c_uint8
+        lib.oracle_dedisp_delays.argtypes = [i64, dbl, dbl, dbl, vp, ctypes.c_int32, vp]
+        lib.oracle_dedisp_delays.restype = i32
+        lib.oracle_dedisperse.argtypes = [i32, vp, i64, i64, i64, vp, ctypes.c_int32, i64, vp]
+        lib.oracle_dedisperse.restype = i32
+        lib.oracle_series_stats.argtypes = [i32, vp, ctypes.c_int32, i64, vp, vp, vp, vp, vp]
+        lib.oracle_series_stats.restype = i32
         _lib = lib
     return _lib
 
@@ -106,3 +113,47 @@ def mean_f32(x: np.ndarray) -> np.float32:
 def mean_u8(x: np.ndarray) -> int:
     x = np.ascontiguousarray(x, dtype=np.uint8)
     return int(_load().oracle_mean_u8(x.ctypes.data, x.size))
+
+
+def dedisp_delays(nchan: int, f_low_mhz: float, chan_bw_mhz: float, tsamp_s: float, dms) -> np.ndarray:
+    """Eq. 2 delays in samples, int32 [ndm][nchan] (channel 0 lowest, reference
+    = top channel centre, nearest sample, ties to even)."""
+    dms = np.ascontiguousarray(dms, dtype=np.float64)
+    out = np.zeros((dms.size, nchan), dtype=np.int32)
+    rc = _load().oracle_dedisp_delays(nchan, f_low_mhz, chan_bw_mhz, tsamp_s, dms.ctypes.data, dms.size,
+                                      out.ctypes.data)
+    if rc != 0:
+        raise ValueError("oracle rejected the dedispersion arguments")
+    return out
+
+
+def dedisperse(x: np.ndarray, delays: np.ndarray, nsamp: int | None = None) -> np.ndarray:
+    """Dedispersed series [ndm][nout] of beam x [C][stride]: int64 sums for
+    uint8 input, double sums in channel order for float32 input."""
+    x = np.ascontiguousarray(x)
+    delays = np.ascontiguousarray(delays, dtype=np.int32)
+    C, stride = x.shape
+    T = stride if nsamp is None else int(nsamp)
+    nout = T - int(delays.max())
+    out = np.zeros((delays.shape[0], max(nout, 1)), dtype=np.int64 if x.dtype == np.uint8 else np.float64)
+    rc = _load().oracle_dedisperse(_DT[x.dtype], x.ctypes.data, C, T, stride, delays.ctypes.data,
+                                   delays.shape[0], nout, out.ctypes.data)
+    if rc != 0:
+        raise ValueError("oracle rejected the dedispersion arguments")
+    return out
+
+
+def series_stats(series: np.ndarray) -> dict:
+    """Per series (row): snr, peak, peak_t, mean, std."""
+    series = np.ascontiguousarray(series)
+    nd, n = series.shape
+    dt = 0 if series.dtype == np.int64 else 1
+    if dt == 1:
+        series = series.astype(np.float64)
+    r = {k: np.zeros(nd, dtype=np.float64) for k in ("snr", "peak", "mean", "std")}
+    r["peak_t"] = np.zeros(nd, dtype=np.int64)
+    rc = _load().oracle_series_stats(dt, series.ctypes.data, nd, n, r["snr"].ctypes.data, r["peak"].ctypes.data,
+                                     r["peak_t"].ctypes.data, r["mean"].ctypes.data, r["std"].ctypes.data)
+    if rc != 0:
+        raise ValueError("oracle rejected the series")
+    return r
