@@ -320,10 +320,19 @@ __device__ inline void td_row_f32(const DevBeam& bm, int64_t c, const Segment& s
             if (!TWO) {
                 const u128 Sa = St < 0 ? (u128)(-St) : (u128)St;
                 const u128 D = (u128)n * Qt - Sa * Sa;
-                const u128 z = zmax_k2(1, D, st.kx, kZcap);
-                H = f32_round_ratio(St + (i128)z, n, e, kRD);
-                Lo = f32_round_ratio(St - (i128)z, n, e, kRU);
-                rm = f32_round_ratio(St, n, e, kRN);
+                // certified FP64 evaluation of the cut and the mean, else exact
+                bool cert = false;
+                if (st.kx.mode == 0) {
+                    const double Sd = i128_to_double(St);
+                    const double zr = st.kx.k * sqrt(u128_to_double(D));
+                    cert = f32_cut_fast(Sd, zr, (double)n, e, &H, &Lo) && f32_mean_fast(Sd, (double)n, e, &rm);
+                }
+                if (!cert) {
+                    const u128 z = zmax_k2(1, D, st.kx, kZcap);
+                    H = f32_round_ratio(St + (i128)z, n, e, kRD);
+                    Lo = f32_round_ratio(St - (i128)z, n, e, kRU);
+                    rm = f32_round_ratio(St, n, e, kRN);
+                }
             } else {
                 // units of the second window: S = S0 * 2^24 + S1, Q = Q0 * 2^48 + Q1
                 const i128 Sc = St * ((i128)1 << 24) + St1;
@@ -492,7 +501,8 @@ __device__ inline int fd_column_f32(float (&x)[BPL][B], uint32_t (&fw)[BPL][B / 
     for (int s = 0; s < seg.n_fd; s++) {
         const SegStep& st = seg.fd[s];
         i128 S[BPL];
-        u128 z;
+        u128 z = 0, Rv = 0;
+        double zr = 0.0;
         if (!TWO) {
             u128 V = 0;
 #pragma unroll
@@ -512,8 +522,11 @@ __device__ inline int fd_column_f32(float (&x)[BPL][B], uint32_t (&fw)[BPL][B / 
                 if (act[kk]) V += (u128)B * Qb - Sa * Sa;
             }
             V = group_add_u128(V, G2);
-            // sum over the time sample of Z_c^2 = B * sum_b (B*Q_b - S_b^2)
-            z = zmax_k2(C, (u128)B * V, st.kx, kZcap);
+            // sum over the time sample of Z_c^2 = B * sum_b (B*Q_b - S_b^2);
+            // the integer radius z is only needed where the FP64 cut is not
+            // certified (below)
+            Rv = (u128)B * V;
+            zr = st.kx.mode == 0 ? st.kx.k * sqrt(u128_to_double(Rv) / (double)C) : 0.0;
         } else {
             U512 V = u512_from(0);
 #pragma unroll
@@ -543,17 +556,39 @@ __device__ inline int fd_column_f32(float (&x)[BPL][B], uint32_t (&fw)[BPL][B / 
         }
         const int bit = st.bit;
         uint32_t bad = 0;
+        // cut interval per bin: certified FP64 evaluation, else exact
+        float Hs[BPL], Los[BPL];
+        bool cert[BPL];
+        bool need = false;
+#pragma unroll
+        for (int kk = 0; kk < BPL; kk++) {
+            cert[kk] = false;
+            Hs[kk] = Los[kk] = 0.0f;
+            if (!TWO && st.kx.mode == 0 && act[kk])
+                cert[kk] = f32_cut_fast((double)(int64_t)S[kk], zr, (double)B, e, &Hs[kk], &Los[kk]);
+            need |= act[kk] && !cert[kk];
+        }
+        if (need) {
+            if (!TWO) z = zmax_k2(C, Rv, st.kx, kZcap);
+#pragma unroll
+            for (int kk = 0; kk < BPL; kk++) {
+                if (!act[kk] || cert[kk]) continue;
+                Hs[kk] = f32_round_ratio(S[kk] + (i128)z, B, e, kRD);
+                Los[kk] = f32_round_ratio(S[kk] - (i128)z, B, e, kRU);
+            }
+        }
 #pragma unroll
         for (int kk = 0; kk < BPL; kk++) {
             if (!act[kk]) continue;
-            const float H = f32_round_ratio(S[kk] + (i128)z, B, e, kRD);
-            const float Lo = f32_round_ratio(S[kk] - (i128)z, B, e, kRU);
+            const float H = Hs[kk], Lo = Los[kk];
             uint64_t fm = 0;
 #pragma unroll
             for (int j = 0; j < B; j++) fm |= (uint64_t)(x[kk][j] < Lo || x[kk][j] > H) << j;
             if (!fm) continue;
-            const float r = st.replace == RFIM_REPLACE_MEDIAN ? bin_median<B>(x[kk])
-                                                              : f32_round_ratio(S[kk], B, e, kRN);
+            float r;
+            if (st.replace == RFIM_REPLACE_MEDIAN) r = bin_median<B>(x[kk]);
+            else if (TWO || !f32_mean_fast((double)(int64_t)S[kk], (double)B, e, &r))
+                r = f32_round_ratio(S[kk], B, e, kRN);
             if (below_window(__float_as_uint(r), thr2)) bad |= 1u;
             else if (!TWO && below_window(__float_as_uint(r), thr)) bad |= 2u;
 #pragma unroll

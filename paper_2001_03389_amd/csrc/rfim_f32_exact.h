@@ -250,6 +250,77 @@ __device__ inline u128 zmax_k2(u128 M, u128 R, const KExact& kx, u128 zcap) {
     }
 }
 
+// ---- FP64 evaluation of the cut with a certified rounding ------------------
+// A window value x (an integer a in units u = 2^e) is kept iff
+// |den*a - S| <= zr with zr = k*sqrt(R/M) the real cut radius, i.e. iff
+// RU((S - zr)*u/den) <= x <= RD((S + zr)*u/den): for x on the u grid the
+// comparison with the real bound and with the largest integer below it agree.
+// These bounds (and the mean's rounding) are evaluated in FP64 with an error
+// bound; when both ends of the error interval round to the same float32, that
+// float32 is the exact rounding, otherwise the caller takes the exact integer
+// path.  With the 2^-44 relative margin below, an FP64 evaluation is about
+// 2^-21 likely to miss certification, so the exact path becomes rare.
+
+// nearest float32 at or below / at or above d (RN conversion, then one step
+// back when it landed on the wrong side; +-inf beyond the float32 range)
+__device__ inline float f32_step_down(float f) {
+    const uint32_t b = __float_as_uint(f);
+    if (f == 0.0f) return __uint_as_float(0x80000001u);
+    return __uint_as_float(f > 0.0f ? b - 1u : b + 1u);
+}
+__device__ inline float f32_step_up(float f) {
+    const uint32_t b = __float_as_uint(f);
+    if (f == 0.0f) return __uint_as_float(0x00000001u);
+    return __uint_as_float(f > 0.0f ? b + 1u : b - 1u);
+}
+__device__ inline float f32_rd(double d) {
+    const float f = (float)d;
+    return (double)f > d ? f32_step_down(f) : f;
+}
+__device__ inline float f32_ru(double d) {
+    const float f = (float)d;
+    return (double)f < d ? f32_step_up(f) : f;
+}
+
+// rounding in `mode` of a real known to lie in [t - E, t + E], when both ends
+// round to the same float32 (bit for bit)
+__device__ inline bool f32_round_cert(double t, double E, int mode, float* out) {
+    const double a = t - E, b = t + E;
+    float fa, fb;
+    if (mode == kRD) {
+        fa = f32_rd(a);
+        fb = f32_rd(b);
+    } else if (mode == kRU) {
+        fa = f32_ru(a);
+        fb = f32_ru(b);
+    } else {
+        fa = (float)a;
+        fb = (float)b;
+    }
+    *out = fa;
+    return __float_as_uint(fa) == __float_as_uint(fb);
+}
+
+__device__ inline double i128_to_double(i128 v) {
+    const double m = u128_to_double(v < 0 ? (u128)(-v) : (u128)v);
+    return v < 0 ? -m : m;
+}
+
+// Cut interval [Lo, H] (kRU / kRD roundings of (S -+ zr) * 2^e / den) from
+// Sd = S and zr = k*sqrt(R/M) in FP64 (each within a relative 2^-49 of the
+// real value); false when either end is not certified.
+__device__ inline bool f32_cut_fast(double Sd, double zr, double den, int e, float* H, float* Lo) {
+    const double E = ldexp((fabs(Sd) + zr) / den, e) * 0x1p-44;
+    const double th = ldexp((Sd + zr) / den, e), tl = ldexp((Sd - zr) / den, e);
+    return f32_round_cert(th, E, kRD, H) && f32_round_cert(tl, E, kRU, Lo);
+}
+
+// RN(S * 2^e / den) to float32 from Sd = S in FP64
+__device__ inline bool f32_mean_fast(double Sd, double den, int e, float* r) {
+    const double E = ldexp(fabs(Sd) / den, e) * 0x1p-44;
+    return f32_round_cert(ldexp(Sd / den, e), E, kRN, r);
+}
+
 // ---- wider statistics (two windows) ----------------------------------------
 // A row or time sample whose values reach more than 24 exponents below its
 // largest value keeps a second window 24 exponents lower (unit u1 = u / 2^24);
