@@ -293,6 +293,48 @@ const char* rfim_status_string(rfim_status s);
 /* Library version as "major.minor.patch" (static storage). */
 const char* rfim_version(void);
 
+/* ---- Dedispersion and detection (the stage after RFI mitigation) ------------
+ * Section I and Eq. 2: a dispersed pulse reaches channel c, centred at
+ * f_c = f_low + (c + 1/2) * chan_bw (MHz, channel 0 lowest), later than the
+ * top channel's centre f_top by k_DM * DM * (f_c^-2 - f_top^-2) seconds with
+ * k_DM = 4.15e3 MHz^2 pc^-1 cm^3 s; incoherent dedispersion shifts every
+ * channel back by its delay (in samples: the delay over tsamp, rounded to the
+ * nearest integer, ties to even, evaluated in FP64) and sums the channels.
+ * Section V-A uses the dedispersed series to show that mitigation keeps a
+ * dispersed pulse detectable. */
+typedef struct rfim_dedisp rfim_dedisp; /* opaque: delay tables of one band and DM list */
+
+/* Computes the delays of every trial DM (dms[0..ndm), 1 <= ndm <= 65535,
+ * each finite and >= 0) for nchan channels (1 <= nchan < 2^23) and uploads the library's device
+ * tables (allocates).  INVALID_ARG for arguments outside these domains or a
+ * delay beyond 2^31 - 1 samples. */
+rfim_status rfim_dedisp_create(int64_t nchan, double f_low_mhz, double chan_bw_mhz, double tsamp_s,
+                               const double* dms, int32_t ndm, rfim_dedisp** out);
+rfim_status rfim_dedisp_destroy(rfim_dedisp* dd);
+
+/* Host copy of the delays, [ndm][nchan] samples (host_delays may be NULL),
+ * and the largest of them (max_delay may be NULL). */
+rfim_status rfim_dedisp_delays(const rfim_dedisp* dd, int32_t* host_delays, int32_t* max_delay);
+
+/* series[d][t] = sum over channels c in ascending order of beam[c][t +
+ * delay_d(c)] for t in [0, nout), every trial d: device output [ndm][nout],
+ * int32 for uint8 beams (exact) or double for float32 beams (FP64 sums added
+ * in channel order).  Reads beam->in only ([nchan][row_stride], nchan as at
+ * creation); requires 1 <= nout <= nsamp - max_delay, else INVALID_ARG.
+ * Asynchronous on `stream`; the current device must be the creation device. */
+rfim_status rfim_dedisperse(const rfim_dedisp* dd, const rfim_beam* beam, int64_t nout, void* series,
+                            void* stream);
+
+/* Detection statistics of nseries device series of n values each, stored
+ * contiguously ([nseries][n]); dtype RFIM_U8 names int32 series (as
+ * rfim_dedisperse writes for uint8 beams), RFIM_F32 double series.  Device
+ * output stats[i][0..5) = SNR = (peak - mean) / std (0 when std = 0), peak
+ * (the largest value), its first index, mean, population standard deviation.
+ * int32 series: exact integer sums, then FP64; double series: two FP64
+ * passes.  1 <= n < 2^32. */
+rfim_status rfim_series_stats(int32_t dtype, const void* series, int32_t nseries, int64_t n, double* stats,
+                              void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -124,6 +124,14 @@ def lib() -> ctypes.CDLL:
                   "rfim_plan_kernel_times", "rfim_plan_capture", "rfim_plan_replay", "rfim_autotune",
                   "rfim_tune_lookup", "rfim_tune_store"):
             getattr(L, f).restype = st
+        L.rfim_dedisp_create.argtypes = [i64, dbl, dbl, dbl, ctypes.POINTER(dbl), i32, ctypes.POINTER(vp)]
+        L.rfim_dedisp_destroy.argtypes = [vp]
+        L.rfim_dedisp_delays.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]
+        L.rfim_dedisperse.argtypes = [vp, PB, i64, vp, vp]
+        L.rfim_series_stats.argtypes = [i32, vp, i32, i64, vp, vp]
+        for f in ("rfim_dedisp_create", "rfim_dedisp_destroy", "rfim_dedisp_delays", "rfim_dedisperse",
+                  "rfim_series_stats"):
+            getattr(L, f).restype = st
         L.rfim_status_string.argtypes = [st]
         L.rfim_status_string.restype = ctypes.c_char_p
         L.rfim_version.argtypes = []
@@ -447,3 +455,72 @@ class Serve:
             self.close()
         except Exception:
             pass
+
+
+# ------------------------------------------------------------ dedispersion
+class Dedisp:
+    """Incoherent dedispersion over a list of trial DMs (rfim_dedisp_create,
+    rfim_dedisperse; Eq. 2 delays relative to the top channel's centre).
+    Channel c is centred at f_low + (c + 1/2) * chan_bw MHz, channel 0 lowest."""
+
+    def __init__(self, nchan: int, dms: Sequence[float], f_low_mhz: float = 1220.0,
+                 chan_bw_mhz: float | None = None, tsamp_s: float = 81.92e-6):
+        import numpy as np
+        bw = 300.0 / nchan if chan_bw_mhz is None else float(chan_bw_mhz)
+        d = np.ascontiguousarray(dms, dtype=np.float64)
+        h = ctypes.c_void_p()
+        _check(lib().rfim_dedisp_create(int(nchan), float(f_low_mhz), bw, float(tsamp_s),
+                                        d.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), d.size,
+                                        ctypes.byref(h)), "rfim_dedisp_create")
+        self.handle, self.nchan, self.ndm = h, int(nchan), int(d.size)
+        mx = ctypes.c_int32()
+        _check(lib().rfim_dedisp_delays(self.handle, None, ctypes.byref(mx)), "rfim_dedisp_delays")
+        self.max_delay = int(mx.value)
+
+    def delays(self):
+        """Host copy of the delays, int32 [ndm][nchan] samples."""
+        import numpy as np
+        out = np.zeros((self.ndm, self.nchan), dtype=np.int32)
+        _check(lib().rfim_dedisp_delays(self.handle, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), None),
+               "rfim_dedisp_delays")
+        return out
+
+    def run(self, beam, nout: int | None = None, nsamp: int | None = None, series=None, stream=None):
+        """Dedispersed series [ndm][nout] of a [nchan][row_stride] beam tensor:
+        int32 for uint8 beams, float64 for float32 beams (rfim_dedisperse)."""
+        import torch
+        b = make_beam(beam, None, None, nsamp)
+        n = int(b.nsamp - self.max_delay) if nout is None else int(nout)
+        dt = torch.int32 if beam.dtype == torch.uint8 else torch.float64
+        if series is None:
+            series = torch.empty((self.ndm, max(n, 1)), dtype=dt, device=beam.device)
+        elif series.dtype != dt or not series.is_contiguous() or series.numel() < self.ndm * n:
+            raise ValueError(f"series must be a contiguous {dt} tensor of at least {self.ndm} x {n} values")
+        _check(lib().rfim_dedisperse(self.handle, ctypes.byref(b), n, series.data_ptr(), _stream_handle(stream)),
+               "rfim_dedisperse")
+        return series
+
+    def close(self):
+        if self.handle:
+            lib().rfim_dedisp_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def series_stats(series, stream=None):
+    """[nseries][5] float64 device tensor of (SNR, peak, first peak index,
+    mean, std) per row of a contiguous int32 or float64 series tensor
+    (rfim_series_stats)."""
+    import torch
+    if series.dim() != 2 or not series.is_contiguous() or series.dtype not in (torch.int32, torch.float64):
+        raise ValueError("series must be a contiguous 2-D int32 or float64 tensor")
+    out = torch.empty((series.shape[0], 5), dtype=torch.float64, device=series.device)
+    dt = RFIM_U8 if series.dtype == torch.int32 else RFIM_F32
+    _check(lib().rfim_series_stats(dt, series.data_ptr(), series.shape[0], series.shape[1], out.data_ptr(),
+                                   _stream_handle(stream)), "rfim_series_stats")
+    return out
