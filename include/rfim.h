@@ -58,7 +58,8 @@ typedef enum {
     RFIM_ERR_OUT_OF_MEMORY = -3, /* workspace allocation failed */
     RFIM_ERR_DEVICE = -4,        /* HIP runtime or device error */
     RFIM_ERR_BUDGET = -5,        /* admission refused: HBM budget exhausted */
-    RFIM_ERR_MISMATCH = -6       /* auto-tuner: a candidate configuration's output differs from the default's */
+    RFIM_ERR_MISMATCH = -6,      /* auto-tuner: a candidate configuration's output differs from the default's */
+    RFIM_ERR_SCRATCH = -7        /* rfim_pipeline_run_noalloc: the call does not fit its fixed scratch array */
 } rfim_status;
 
 typedef enum { RFIM_U8 = 0, RFIM_F32 = 1 } rfim_dtype;
@@ -110,6 +111,28 @@ rfim_status rfim_fd_sigma_cut(const rfim_beam* beams, int32_t nbeams, double k, 
  * created for the same beam shapes and steps. */
 rfim_status rfim_pipeline_run(const rfim_beam* beams, int32_t nbeams, const rfim_step* steps,
                               int32_t nsteps, rfim_plan* plan, void* stream);
+
+/* Bytes of the fixed device scratch array of rfim_pipeline_run_noalloc. */
+#define RFIM_NOALLOC_SCRATCH_BYTES (32u << 20)
+
+/* rfim_pipeline_run for callers that cannot allocate: code under HIP-graph
+ * capture, tight serving loops and harnesses that forbid hipMalloc.  It
+ * calls no hipMalloc, hipHostMalloc or hipFree: the workspace and launch
+ * tables of the call live in a file-scope device array of
+ * RFIM_NOALLOC_SCRATCH_BYTES bytes (32 MiB), one copy per GPU, held from the
+ * library's load until the process ends; launch tables reach it as kernel
+ * arguments.  Beams, steps, results and argument errors are those of
+ * rfim_pipeline_run(beams, nbeams, steps, nsteps, NULL, stream), with the
+ * default kernel configuration and no flag counts.  Returns
+ * RFIM_ERR_SCRATCH, before enqueuing anything, when the call needs more
+ * (per TD step 4 bytes per uint8 row and 16 per float32 row; 16 bytes per
+ * float32 row and per float32 time sample; about 100 bytes of launch table
+ * per beam and run: 16 float32 beams of 4096 x 65536 need about 22 MB).  Every call on a
+ * GPU uses that GPU's one array and leaves its contents behind: calls that
+ * overlap on one GPU (two streams, two host threads) race and must be
+ * serialised by the caller; calls in order on one stream are safe. */
+rfim_status rfim_pipeline_run_noalloc(const rfim_beam* beams, int32_t nbeams, const rfim_step* steps,
+                                      int32_t nsteps, void* stream);
 
 /* Creates a plan for beams of these shapes and dtypes (pointers are ignored,
  * except that a run must pass flags exactly where the shapes did) and this

@@ -18,6 +18,8 @@ LIB_PATH = os.path.join(HERE, "librfim.so")
 
 RFIM_OK, RFIM_ERR_INVALID_ARG, RFIM_ERR_UNSUPPORTED = 0, -1, -2
 RFIM_ERR_OUT_OF_MEMORY, RFIM_ERR_DEVICE, RFIM_ERR_BUDGET, RFIM_ERR_MISMATCH = -3, -4, -5, -6
+RFIM_ERR_SCRATCH = -7
+RFIM_NOALLOC_SCRATCH_BYTES = 32 << 20
 RFIM_U8, RFIM_F32 = 0, 1
 RFIM_REPLACE_MEAN, RFIM_REPLACE_MEDIAN = 0, 1
 RFIM_TD, RFIM_FD = 0, 1
@@ -94,6 +96,7 @@ def lib() -> ctypes.CDLL:
         L.rfim_td_sigma_cut.argtypes = [PB, i32, dbl, i32, vp]
         L.rfim_fd_sigma_cut.argtypes = [PB, i32, dbl, i64, i32, vp]
         L.rfim_pipeline_run.argtypes = [PB, i32, PS, i32, vp, vp]
+        L.rfim_pipeline_run_noalloc.argtypes = [PB, i32, PS, i32, vp]
         L.rfim_plan_create.argtypes = [PB, i32, PS, i32, ctypes.c_char_p, ctypes.POINTER(vp)]
         L.rfim_plan_destroy.argtypes = [vp]
         L.rfim_plan_flag_counts.argtypes = [vp, ctypes.POINTER(ctypes.c_uint64)]
@@ -119,7 +122,8 @@ def lib() -> ctypes.CDLL:
         for f in ("rfim_plan_replay_on", "rfim_serve_create", "rfim_serve_submit", "rfim_serve_poll",
                   "rfim_serve_drain", "rfim_serve_get_stats", "rfim_serve_destroy"):
             getattr(L, f).restype = st
-        for f in ("rfim_td_sigma_cut", "rfim_fd_sigma_cut", "rfim_pipeline_run", "rfim_plan_create",
+        for f in ("rfim_td_sigma_cut", "rfim_fd_sigma_cut", "rfim_pipeline_run", "rfim_pipeline_run_noalloc",
+                  "rfim_plan_create",
                   "rfim_plan_destroy", "rfim_plan_flag_counts", "rfim_plan_set_timing",
                   "rfim_plan_kernel_times", "rfim_plan_capture", "rfim_plan_replay", "rfim_autotune",
                   "rfim_tune_lookup", "rfim_tune_store"):
@@ -291,6 +295,17 @@ def rfim_pipeline_run(inputs: Sequence, steps: Sequence, outputs: Sequence | Non
     rc = lib().rfim_pipeline_run(arr, n, st, len(steps), plan.handle if plan else None,
                                  _stream_handle(stream))
     _check(rc, "rfim_pipeline_run")
+
+
+def rfim_pipeline_run_noalloc(inputs: Sequence, steps: Sequence, outputs: Sequence | None = None,
+                              flags: Sequence | None = None, nsamp=None, stream=None) -> None:
+    """Run ``steps`` in order on every beam without allocating anything: the
+    workspace is the library's fixed per-GPU scratch array
+    (rfim_pipeline_run_noalloc).  Calls that overlap on one GPU race."""
+    arr, n = _beams(inputs, outputs, flags, nsamp)
+    st = make_steps(steps)
+    _check(lib().rfim_pipeline_run_noalloc(arr, n, st, len(steps), _stream_handle(stream)),
+           "rfim_pipeline_run_noalloc")
 
 
 def rfim_td_sigma_cut(inputs: Sequence, k: float, replace="mean", outputs=None, flags=None,

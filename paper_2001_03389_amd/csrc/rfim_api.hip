@@ -889,6 +889,22 @@ rfim_status check_plan_match(const rfim_plan* plan, const rfim_beam* beams, int3
     return RFIM_OK;
 }
 
+// With no step to run, out-of-place beams still receive a copy of the input
+// and flags are cleared.
+rfim_status copy_through(const rfim_beam* beams, int32_t nbeams, hipStream_t stream) {
+    for (int i = 0; i < nbeams; i++) {
+        const rfim_beam& b = beams[i];
+        size_t es = elem_size(b.dtype);
+        if (b.in != b.out &&
+            hipMemcpy2DAsync(b.out, b.row_stride * es, b.in, b.row_stride * es, b.nsamp * es, b.nchan,
+                             hipMemcpyDeviceToDevice, stream) != hipSuccess)
+            return RFIM_ERR_DEVICE;
+        if (b.flags && hipMemset2DAsync(b.flags, b.row_stride, 0, b.nsamp, b.nchan, stream) != hipSuccess)
+            return RFIM_ERR_DEVICE;
+    }
+    return RFIM_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -902,6 +918,7 @@ const char* rfim_status_string(rfim_status s) {
         case RFIM_ERR_DEVICE: return "HIP device or runtime error";
         case RFIM_ERR_BUDGET: return "HBM budget exhausted";
         case RFIM_ERR_MISMATCH: return "a tuning candidate's output differs from the default configuration's";
+        case RFIM_ERR_SCRATCH: return "the call needs more than the fixed scratch array of the no-allocation entry point";
     }
     return "unknown status";
 }
@@ -912,22 +929,7 @@ rfim_status rfim_pipeline_run(const rfim_beam* beams, int32_t nbeams, const rfim
                               int32_t nsteps, rfim_plan* plan, void* stream) {
     rfim_status st = validate(beams, nbeams, steps, nsteps);
     if (st != RFIM_OK) return st;
-    if (nbeams == 0 || nsteps == 0) {
-        // nothing to cut: out-of-place beams still receive a copy of the input
-        for (int i = 0; i < nbeams; i++) {
-            const rfim_beam& b = beams[i];
-            size_t es = elem_size(b.dtype);
-            if (b.in != b.out &&
-                hipMemcpy2DAsync(b.out, b.row_stride * es, b.in, b.row_stride * es, b.nsamp * es,
-                                 b.nchan, hipMemcpyDeviceToDevice, (hipStream_t)stream) != hipSuccess)
-                return RFIM_ERR_DEVICE;
-            if (b.flags &&
-                hipMemset2DAsync(b.flags, b.row_stride, 0, b.nsamp, b.nchan, (hipStream_t)stream) !=
-                    hipSuccess)
-                return RFIM_ERR_DEVICE;
-        }
-        return RFIM_OK;
-    }
+    if (nbeams == 0 || nsteps == 0) return copy_through(beams, nbeams, (hipStream_t)stream);
     if (plan) {
         st = check_plan_match(plan, beams, nbeams, steps, nsteps);
         if (st != RFIM_OK) return st;
@@ -1202,3 +1204,80 @@ rfim_status rfim_plan_kernel_times(rfim_plan* plan, int32_t kind, uint64_t* laun
 
 }  // extern "C"
 
+
+// ---------------------------------------------------------------------------
+// rfim_pipeline_run_noalloc: the plan-less run with its workspace and launch
+// tables in a fixed device array instead of allocated memory.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[RFIM_NOALLOC_SCRATCH_BYTES];
+
+namespace rfim {
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch[kMaxDevices] = {};
+
+// Device address of this device's copy of `scratch`.  In host code the
+// array's name is only a host-side stand-in: kernels and copies must use the
+// address the runtime returns for the current device.
+rfim_status scratch_of_current_device(void** out) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return RFIM_ERR_DEVICE;
+    if (dev < 0 || dev >= kMaxDevices) return RFIM_ERR_UNSUPPORTED;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) return dev_err(e != hipSuccess ? e : hipErrorInvalidSymbol);
+        g_scratch[dev] = p;
+    }
+    *out = g_scratch[dev];
+    return RFIM_OK;
+}
+
+// Launch tables reach the device as kernel arguments (copied at launch), so
+// no pinned staging buffer is needed.
+constexpr int kBlobWords = 240;
+struct BlobChunk {
+    uint64_t w[kBlobWords];
+};
+
+__global__ void k_store_words(uint64_t* __restrict__ dst, BlobChunk c, int n) {
+    const int i = threadIdx.x;
+    if (i < n) dst[i] = c.w[i];
+}
+
+}  // namespace
+}  // namespace rfim
+
+extern "C" rfim_status rfim_pipeline_run_noalloc(const rfim_beam* beams, int32_t nbeams, const rfim_step* steps,
+                                                 int32_t nsteps, void* stream) {
+    rfim_status st = validate(beams, nbeams, steps, nsteps);
+    if (st != RFIM_OK) return st;
+    const hipStream_t s = (hipStream_t)stream;
+    if (nbeams == 0 || nsteps == 0) return copy_through(beams, nbeams, s);
+    LaunchPlan lp;
+    st = make_launch_plan(beams, nbeams, steps, nsteps, false, default_tune(), &lp);
+    if (st != RFIM_OK) return st;
+    Program pg;
+    build_program(beams, nbeams, lp, false, pg);
+    static_assert(sizeof(DevBeam) % 8 == 0, "launch tables are copied in 8-byte words");
+    const size_t blob_off = (lp.work_bytes + 255) & ~(size_t)255;
+    const size_t blob_bytes = sizeof(DevBeam) * pg.blob.size();
+    if (blob_off + blob_bytes > (size_t)RFIM_NOALLOC_SCRATCH_BYTES) return RFIM_ERR_SCRATCH;
+    void* base = nullptr;
+    st = scratch_of_current_device(&base);
+    if (st != RFIM_OK) return st;
+    char* wbase = (char*)base;
+    const uint64_t* words = (const uint64_t*)pg.blob.data();
+    const size_t nwords = blob_bytes / 8;
+    for (size_t w0 = 0; w0 < nwords; w0 += kBlobWords) {
+        BlobChunk c;
+        const int n = (int)std::min<size_t>(kBlobWords, nwords - w0);
+        std::memcpy(c.w, words + w0, (size_t)n * 8);
+        hipLaunchKernelGGL(k_store_words, dim3(1), dim3(256), 0, s, (uint64_t*)(wbase + blob_off) + w0, c, n);
+        if (hipGetLastError() != hipSuccess) return RFIM_ERR_DEVICE;
+    }
+    return enqueue(pg, lp, (const DevBeam*)(wbase + blob_off), wbase, nullptr, s, false);
+}
