@@ -452,6 +452,7 @@ def run_workload(rf, torch, dev, name, steps_timed, warmup, replace="mean", inpl
     torch.cuda.synchronize()
     algo = {rf.RFIM_KERNEL_TD_ROWS_U8: nel_u8 * 1,        # reads every sample once
             rf.RFIM_KERNEL_FUSED_U8: nel_u8 * 2,          # reads and writes every sample
+            rf.RFIM_KERNEL_PERSIST_U8: nel_u8 * 2,        # both passes: one algorithmic read and write
             rf.RFIM_KERNEL_TD_ROWS_F32: nel_f32 * 4,
             rf.RFIM_KERNEL_FUSED_F32: nel_f32 * 8}
     kernels = kernel_table(rf, plan, ins, algo)

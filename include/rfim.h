@@ -160,7 +160,8 @@ rfim_status rfim_plan_replay_on(rfim_plan* plan, const rfim_beam* beams, int32_t
 
 /* Auto-tuner (Section III: parameters tuned per setup and platform, the
  * configurations saved for production).  Times every candidate kernel
- * configuration for these shapes and steps on freshly allocated beams filled
+ * configuration (uint8 tile cap and LDS budget, uint8 schedule, float32 LDS
+ * budget and tile cap) for these shapes and steps on freshly allocated beams filled
  * on the device with a deterministic pattern shaped like channelised
  * telescope data (per-channel level and spread, narrow-band channels,
  * broadband impulses), and stores the fastest in the JSON cache file
@@ -175,15 +176,20 @@ rfim_status rfim_plan_replay_on(rfim_plan* plan, const rfim_beam* beams, int32_t
 rfim_status rfim_autotune(const rfim_beam* shapes, int32_t nbeams, const rfim_step* steps, int32_t nsteps,
                           const char* tune_cache_path, void* stream, double* best_ms);
 
-/* Tuning-cache access without a GPU: rfim_tune_lookup fills out4 =
- * {uint8 tile cap (samples), float32 LDS budget (bytes), float32 tile cap,
- * uint8 LDS budget (bytes)} for the key of these shapes and steps
- * (RFIM_ERR_UNSUPPORTED: no entry or no file); rfim_tune_store adds or
- * replaces that entry (RFIM_ERR_INVALID_ARG for values out of range). */
+/* Number of tuning parameters of a cache entry. */
+#define RFIM_TUNE_NPARAMS 5
+
+/* Tuning-cache access without a GPU: rfim_tune_lookup fills
+ * params[RFIM_TUNE_NPARAMS] = {uint8 tile cap (samples), float32 LDS budget
+ * (bytes), float32 tile cap, uint8 LDS budget (bytes), uint8 schedule (0 = a
+ * TD pass then a fused pass over all beams of the call, 1 = one persistent
+ * beam-major launch per run of [TD][FD] steps)} for the key of these shapes
+ * and steps (RFIM_ERR_UNSUPPORTED: no entry or no file); rfim_tune_store adds
+ * or replaces that entry (RFIM_ERR_INVALID_ARG for values out of range). */
 rfim_status rfim_tune_lookup(const char* path, const rfim_beam* shapes, int32_t nbeams, const rfim_step* steps,
-                             int32_t nsteps, int64_t* out4);
+                             int32_t nsteps, int64_t* params);
 rfim_status rfim_tune_store(const char* path, const rfim_beam* shapes, int32_t nbeams, const rfim_step* steps,
-                            int32_t nsteps, const int64_t* params4, double ms);
+                            int32_t nsteps, const int64_t* params, double ms);
 
 /* Per (beam, step) number of replaced samples of the most recent run with
  * this plan, copied to host_out[nbeams * nsteps]; synchronises the plan's
@@ -232,7 +238,8 @@ typedef enum {
     RFIM_KERNEL_FD_WIDE_F32 = 5, /* float32 time samples outside the fast window */
     RFIM_KERNEL_TD_TWO_F32 = 6,  /* float32 rows needing a second fixed-point window */
     RFIM_KERNEL_FD_TWO_F32 = 7,  /* float32 time samples needing a second window */
-    RFIM_KERNEL_KINDS = 8
+    RFIM_KERNEL_PERSIST_U8 = 8,  /* uint8 persistent beam-major launch: TD pass + fused pass */
+    RFIM_KERNEL_KINDS = 9
 } rfim_kernel_kind;
 
 /* Per-kernel timing of a plan (Section V-B reports execution time averaged

@@ -26,10 +26,12 @@ RFIM_TD, RFIM_FD = 0, 1
 RFIM_KERNEL_TD_ROWS_U8, RFIM_KERNEL_FUSED_U8 = 0, 1
 RFIM_KERNEL_TD_ROWS_F32, RFIM_KERNEL_FUSED_F32, RFIM_KERNEL_TD_WIDE_F32, RFIM_KERNEL_FD_WIDE_F32 = 2, 3, 4, 5
 RFIM_KERNEL_TD_TWO_F32, RFIM_KERNEL_FD_TWO_F32 = 6, 7
+RFIM_KERNEL_PERSIST_U8 = 8
 KERNEL_NAMES = {RFIM_KERNEL_TD_ROWS_U8: "k_td_rows_u8", RFIM_KERNEL_FUSED_U8: "k_fused_u8",
                 RFIM_KERNEL_TD_ROWS_F32: "k_td_rows_f32", RFIM_KERNEL_FUSED_F32: "k_fused_f32",
                 RFIM_KERNEL_TD_WIDE_F32: "k_td_wide_f32", RFIM_KERNEL_FD_WIDE_F32: "k_fd_wide_f32",
-                RFIM_KERNEL_TD_TWO_F32: "k_td_two_f32", RFIM_KERNEL_FD_TWO_F32: "k_fd_two_f32"}
+                RFIM_KERNEL_TD_TWO_F32: "k_td_two_f32", RFIM_KERNEL_FD_TWO_F32: "k_fd_two_f32",
+                RFIM_KERNEL_PERSIST_U8: "k_persist_u8"}
 
 
 FD_PATH_NAMES = {0: "none", 1: "u8_bin32_g4", 2: "u8_bin32_g8", 3: "u8_bin32_g16", 4: "u8_vec", 5: "u8_bytes",
@@ -242,11 +244,14 @@ def _shape_array(shapes):
     return arr
 
 
+RFIM_TUNE_NPARAMS = 5
+
+
 def tune_lookup(path: str, shapes: Sequence[rfim_beam], steps: Sequence):
-    """(uint8 tile cap, float32 LDS bytes, float32 tile cap, uint8 LDS bytes)
-    stored in the tuning cache for these shapes and steps, or None
-    (rfim_tune_lookup)."""
-    out = (ctypes.c_int64 * 4)()
+    """(uint8 tile cap, float32 LDS bytes, float32 tile cap, uint8 LDS bytes,
+    uint8 schedule) stored in the tuning cache for these shapes and steps, or
+    None (rfim_tune_lookup)."""
+    out = (ctypes.c_int64 * RFIM_TUNE_NPARAMS)()
     rc = lib().rfim_tune_lookup(path.encode(), _shape_array(shapes), len(shapes), make_steps(steps),
                                 len(steps), out)
     if rc == RFIM_ERR_UNSUPPORTED:
@@ -258,9 +263,11 @@ def tune_lookup(path: str, shapes: Sequence[rfim_beam], steps: Sequence):
 def tune_store(path: str, shapes: Sequence[rfim_beam], steps: Sequence, params, ms: float = 0.0) -> None:
     """Adds or replaces the cache entry of these shapes and steps (rfim_tune_store)."""
     vals = [int(v) for v in params]
-    if len(vals) == 3:
-        vals.append(51200)   # default uint8 LDS budget
-    p = (ctypes.c_int64 * 4)(*vals)
+    defaults = [64, 81920, 64, 51200, 0]   # uint8 LDS budget and schedule may be left out
+    if not 3 <= len(vals) <= RFIM_TUNE_NPARAMS:
+        raise ValueError(f"3 to {RFIM_TUNE_NPARAMS} tuning parameters expected")
+    vals += defaults[len(vals):]
+    p = (ctypes.c_int64 * RFIM_TUNE_NPARAMS)(*vals)
     _check(lib().rfim_tune_store(path.encode(), _shape_array(shapes), len(shapes), make_steps(steps),
                                  len(steps), p, float(ms)), "rfim_tune_store")
 

@@ -29,6 +29,17 @@ hipError_t launch_zero_u64(unsigned long long* p, int64_t n, hipStream_t s) {
     return hipGetLastError();
 }
 
+__global__ void k_or_error(const unsigned* __restrict__ src, unsigned* __restrict__ sticky) {
+    if (threadIdx.x == 0 && *src) *sticky |= *src;
+}
+
+// folds a launch's error word into the workspace's sticky one (read by
+// rfim_plan_flag_counts)
+hipError_t launch_or_error(const unsigned* src, unsigned* sticky, hipStream_t s) {
+    hipLaunchKernelGGL(k_or_error, dim3(1), dim3(64), 0, s, src, sticky);
+    return hipGetLastError();
+}
+
 KExact make_k(double k) {
     // the exact binary value k = mk * 2^ek (mk odd) is kept for every k > 0:
     // the float32 wide path compares against sums far beyond 2^128
@@ -271,6 +282,7 @@ struct Workspace {
         work_cap = 0;
         size_t cap = std::max<size_t>(bytes, (size_t)1 << 20);
         if (hipMalloc(&d_work, cap) != hipSuccess) return RFIM_ERR_OUT_OF_MEMORY;
+        if (hipMemset(d_work, 0, cap) != hipSuccess) return RFIM_ERR_DEVICE;   // sticky error words start clear
         work_cap = cap;
         return RFIM_OK;
     }
@@ -347,6 +359,13 @@ struct LaunchPlan {
     size_t off_u8rec = 0, off_f32rec = 0, off_wide = 0, off_tditems = 0, off_fditems = 0;
     size_t off_tdtiny = 0, off_fdtiny = 0;
     size_t count_bytes = 0, work_bytes = 0;
+    // uint8 persistent schedule: control words [next item per queue, error,
+    // done per uint8 beam] (zeroed before each launch), the sticky error word,
+    // LDS and grid
+    size_t off_ctl = 0, off_err = 0, ctl_words = 0;
+    size_t persist_lds = 0;
+    int persist_grid = 0;
+    uint32_t spin_limit = 1u << 22, wait_extra = 0;
 };
 
 // True when, for every uint8 beam and FD step of the run, each lane's share
@@ -478,6 +497,19 @@ rfim_status make_launch_plan(const rfim_beam* beams, int32_t nbeams, const rfim_
     lp->off_tdtiny = lp->off_fditems + al((size_t)lp->f32_cols * 8);
     lp->off_fdtiny = lp->off_tdtiny + al((size_t)lp->f32_rows * 8);
     lp->work_bytes = lp->off_fdtiny + al((size_t)lp->f32_cols * 8);
+    // the sticky error word of the persistent schedule (zeroed with the workspace)
+    lp->off_err = lp->work_bytes;
+    lp->work_bytes += 256;
+    if (tune.u8_sched == 1 && !lp->u8_beams.empty()) {
+        lp->ctl_words = (kPersistQueues + 1 + lp->u8_beams.size() + 1) / 2;   // 64-bit words
+        lp->off_ctl = lp->work_bytes;
+        lp->work_bytes += al(lp->ctl_words * 8);
+        lp->persist_lds = std::max(lp->u8_lds, td_group_lds_bytes());
+        if (lp->persist_lds > std::min(kLdsMax, lds_limit() - 4096)) return RFIM_ERR_UNSUPPORTED;
+        lp->persist_grid = persist_u8_grid(lp->persist_lds, true);
+        if (const char* e = std::getenv("RFIM_SPIN_LIMIT")) lp->spin_limit = (uint32_t)std::strtoul(e, nullptr, 10);
+        if (const char* e = std::getenv("RFIM_WAIT_EXTRA")) lp->wait_extra = (uint32_t)std::strtoul(e, nullptr, 10);
+    }
     return RFIM_OK;
 }
 
@@ -494,7 +526,7 @@ rfim_status dev_err(hipError_t e) {
 // once for a captured graph), then enqueued on one stream.
 // ---------------------------------------------------------------------------
 enum Op {
-    OP_ZERO_COUNTS, OP_TD_U8, OP_FUSED_U8, OP_ZERO_WIDE, OP_TD_F32, OP_TD_TWO, OP_LIST_ALL, OP_TD_WIDE,
+    OP_ZERO_COUNTS, OP_TD_U8, OP_FUSED_U8, OP_PERSIST_U8, OP_ZERO_WIDE, OP_TD_F32, OP_TD_TWO, OP_LIST_ALL, OP_TD_WIDE,
     OP_FUSED_F32, OP_FD_TWO, OP_FD_WIDE
 };
 
@@ -507,6 +539,7 @@ struct Launch {
     int a = 0, b = 0;   // TD f32 (nt, vpt); fused f32 (B, bpl); wide (grid); list (gidx)
     size_t lds = 0;
     bool vec = false;
+    PersistQueues qs{};   // persistent uint8 launch: item range of each queue
 };
 
 struct Program {
@@ -539,9 +572,38 @@ void build_u8(const rfim_beam* beams, const LaunchPlan& lp, Program& pg) {
         pg.segs.push_back(seg);
         const int table = (int)pg.blob.size();
         const bool vec = fd_vec_ok(beams, lp, seg);
-        int64_t row = 0, tile = 0;
-        for (int j = 0; j < nu8; j++) {
-            const int bi = lp.u8_beams[j];
+        auto items_of = [&](int bi) {
+            const rfim_beam& b = beams[bi];
+            const int64_t ntiles = (b.nsamp + lp.Tt[bi] - 1) / lp.Tt[bi];
+            return (seg.n_td > 0 ? (b.nchan + kBlock / 64 - 1) / (kBlock / 64) : 0) + ntiles;
+        };
+        // table order: the call's order, or for the persistent schedule queue
+        // by queue (beams dealt largest first to the least loaded queue)
+        std::vector<int> order(lp.u8_beams);
+        PersistQueues qs;
+        std::memset(&qs, 0, sizeof qs);
+        if (lp.tune.u8_sched == 1) {
+            std::vector<int> by_size(lp.u8_beams);
+            std::stable_sort(by_size.begin(), by_size.end(), [&](int a, int b) { return items_of(a) > items_of(b); });
+            std::vector<std::vector<int>> q(kPersistQueues);
+            std::vector<int64_t> load(kPersistQueues, 0);
+            for (int bi : by_size) {
+                const int k = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+                q[k].push_back(bi);
+                load[k] += items_of(bi);
+            }
+            order.clear();
+            int64_t base = 0;
+            for (int k = 0; k < kPersistQueues; k++) {
+                std::sort(q[k].begin(), q[k].end());
+                qs.base[k] = base;
+                for (int bi : q[k]) order.push_back(bi);
+                base += load[k];
+            }
+            qs.base[kPersistQueues] = base;
+        }
+        int64_t row = 0, tile = 0, item = 0;
+        for (int bi : order) {
             DevBeam d = dev_beam(beams[bi], si == 0);
             d.row0 = row;
             d.rec0 = row;
@@ -550,9 +612,25 @@ void build_u8(const rfim_beam* beams, const LaunchPlan& lp, Program& pg) {
             d.Cp = lp.Cp[bi];
             d.cidx = bi;
             d.path = fd_path_u8(beams[bi], d.Tt, seg, vec);
+            d.item0 = item;
+            const int64_t ntiles = (d.T + d.Tt - 1) / d.Tt;
+            item += items_of(bi);
             row += d.C;
-            tile += (d.T + d.Tt - 1) / d.Tt;
+            tile += ntiles;
             pg.blob.push_back(d);
+        }
+        if (lp.tune.u8_sched == 1) {
+            Launch L;
+            L.op = OP_PERSIST_U8;
+            L.seg = sidx;
+            L.table = table;
+            L.nbeams = nu8;
+            L.total = item;
+            L.lds = lp.persist_lds;
+            L.vec = vec;
+            L.qs = qs;
+            pg.launches.push_back(L);
+            continue;
         }
         if (seg.n_td > 0) {
             Launch L;
@@ -764,6 +842,19 @@ rfim_status enqueue(const Program& pg, const LaunchPlan& lp, const DevBeam* d_bl
                     return launch_fused_u8(tab, L.nbeams, L.total, seg, u8rec, L.lds, L.vec, counts, kCountStride, stream);
                 });
                 break;
+            case OP_PERSIST_U8: {
+                unsigned* ctl = (unsigned*)(wbase + lp.off_ctl);
+                e = launch_zero_u64((unsigned long long*)ctl, (int64_t)lp.ctl_words, stream);
+                if (e == hipSuccess)
+                    e = timed(RFIM_KERNEL_PERSIST_U8, [&] {
+                        return launch_persist_u8(tab, L.nbeams, L.qs, seg, u8rec, L.lds, L.vec, counts,
+                                                 kCountStride, ctl, lp.spin_limit, lp.wait_extra, lp.persist_grid,
+                                                 stream);
+                    });
+                if (e == hipSuccess)
+                    e = launch_or_error(ctl + kPersistQueues, (unsigned*)(wbase + lp.off_err), stream);
+                break;
+            }
             case OP_ZERO_WIDE:
                 e = launch_zero_u64((unsigned long long*)wide_td_n, 4, stream);
                 break;
@@ -1138,6 +1229,14 @@ rfim_status rfim_plan_flag_counts(const rfim_plan* plan, uint64_t* host_out) {
         return RFIM_ERR_DEVICE;
     for (int b = 0; b < nb; b++)
         for (int s = 0; s < ns; s++) host_out[(size_t)b * ns + s] = tmp[(size_t)b * kCountStride + s];
+    // a persistent launch whose bounded wait ran out left its output incomplete
+    unsigned err = 0;
+    char* ep = (char*)p->ws.d_work + p->lp.off_err;
+    if (hipMemcpy(&err, ep, sizeof err, hipMemcpyDeviceToHost) != hipSuccess) return RFIM_ERR_DEVICE;
+    if (err) {
+        (void)hipMemset(ep, 0, sizeof err);
+        return RFIM_ERR_DEVICE;
+    }
     return RFIM_OK;
 }
 

@@ -60,6 +60,7 @@ struct DevBeam {
     int32_t pad;     // float32: index in the call's float32 beam table (wide lists)
     int32_t path;    // uint8: FD path of the fused kernel (rfim_fd_path), chosen on the host
     int32_t pad2;
+    int64_t item0;   // uint8 persistent schedule: first work item of this beam
 };
 
 // Host launchers (defined in the .hip files).  counts (nullable) receives, per
@@ -73,6 +74,25 @@ hipError_t launch_fused_u8(const DevBeam* d_beams, int nbeams, int64_t total_til
                            const Segment& seg, const uint32_t* d_rec, size_t lds_bytes, bool vec,
                            unsigned long long* d_counts, int count_stride, hipStream_t s);
 hipError_t launch_zero_u64(unsigned long long* p, int64_t n, hipStream_t s);
+// The whole run in one persistent launch (beam-major work items: each beam's
+// TD row groups, then its tiles; a tile waits for its beam's row groups).
+// The launch table lists the beams queue by queue; queue q owns the items
+// [base[q], base[q + 1]).  ctl: zeroed [kPersistQueues + 1 + nbeams] words
+// (next item per queue, error flag, per-beam row groups done); a wait longer
+// than spin_limit polls sets the error flag and stops the work-group;
+// wait_extra (0 in use) raises the count a tile waits for (a test makes the
+// waits run out with it).  grid: work-groups of the launch.
+constexpr int kPersistQueues = 8;   // one per XCD
+struct PersistQueues {
+    int64_t base[kPersistQueues + 1];
+};
+hipError_t launch_persist_u8(const DevBeam* d_beams, int nbeams, const PersistQueues& qs, const Segment& seg,
+                             uint32_t* d_rec, size_t lds_bytes, bool vec, unsigned long long* d_counts,
+                             int count_stride, unsigned* ctl, uint32_t spin_limit, uint32_t wait_extra, int grid,
+                             hipStream_t s);
+// work-groups of the persistent launch that fit the device at once
+int persist_u8_grid(size_t lds_bytes, bool vec);
+size_t td_group_lds_bytes();
 
 // float32 launchers.  TD records are float4 (Lo, H, r, 0) per row and step;
 // wide lists hold (float32 beam index, row or time sample) pairs after a

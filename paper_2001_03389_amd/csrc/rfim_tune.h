@@ -16,10 +16,12 @@ struct TuneParams {
     size_t f32_lds = 81920;      // LDS budget of a float32 fused work-group (bytes)
     int f32_tile_cap = 64;       // largest float32 fused-kernel tile (samples)
     size_t u8_lds = 51200;       // LDS budget of a uint8 fused work-group (bytes)
+    int u8_sched = 0;            // uint8 schedule: 0 = TD pass then fused pass over the whole call,
+                                 // 1 = one persistent beam-major launch per run
 };
 
-// Defaults; RFIM_TILE_T, RFIM_F32_LDS, RFIM_F32_TILE_T and RFIM_U8_LDS in the environment
-// override them (experiments).
+// Defaults; RFIM_TILE_T, RFIM_F32_LDS, RFIM_F32_TILE_T, RFIM_U8_LDS and RFIM_U8_SCHED in the
+// environment override them (experiments).
 TuneParams default_tune();
 
 // Cache key of an ordered list of beam shapes (dtype, nchan, nsamp,

@@ -12,9 +12,9 @@
 // of all candidates' times; rfim_plan_create reads it back.
 //
 // Cache file: one JSON object; each entry sits on its own line,
-//   "<key>": {"u8_tile_cap": 64, "f32_lds": 81920, "f32_tile_cap": 64, "u8_lds": 51200, "ms": 1.5,
-//             "candidates": 9, "table": [[64, 51200, 81920, 64, 1.5], ...]}
-// (table rows: u8 tile cap, u8 LDS, f32 LDS, f32 tile cap, ms per run)
+//   "<key>": {"u8_tile_cap": 64, "f32_lds": 81920, "f32_tile_cap": 64, "u8_lds": 51200, "u8_sched": 0,
+//             "ms": 1.5, "candidates": 9, "table": [[64, 51200, 0, 81920, 64, 1.5], ...]}
+// (table rows: u8 tile cap, u8 LDS, u8 schedule, f32 LDS, f32 tile cap, ms per run)
 #include <algorithm>
 #include <cstdio>
 #include <cstdlib>
@@ -45,6 +45,10 @@ TuneParams default_tune() {
     if (const char* e = std::getenv("RFIM_U8_LDS")) {
         const long v = std::atol(e);
         if (v >= 4096) p.u8_lds = (size_t)v;
+    }
+    if (const char* e = std::getenv("RFIM_U8_SCHED")) {
+        const int v = std::atoi(e);
+        if (v == 0 || v == 1) p.u8_sched = v;
     }
     return p;
 }
@@ -102,16 +106,19 @@ rfim_status tune_cache_lookup(const char* path, const rfim_beam* shapes, int32_t
     const std::string pre = entry_prefix(tune_key(shapes, nbeams, steps, nsteps));
     for (const std::string& l : lines) {
         if (l.compare(0, pre.size(), pre) != 0) continue;
-        double a = 0, b = 0, c = 0, d = 51200;
+        double a = 0, b = 0, c = 0, d = 51200, e = 0;
         if (!field(l, "u8_tile_cap", &a) || !field(l, "f32_lds", &b) || !field(l, "f32_tile_cap", &c))
             return RFIM_ERR_INVALID_ARG;
-        (void)field(l, "u8_lds", &d);   // optional, default budget
-        if (a < 4 || a > 64 || b < 1024 || b > (1 << 20) || c < 4 || c > 64 || d < 4096 || d > (1 << 20))
+        (void)field(l, "u8_lds", &d);     // optional, default budget
+        (void)field(l, "u8_sched", &e);   // optional, default schedule
+        if (a < 4 || a > 64 || b < 1024 || b > (1 << 20) || c < 4 || c > 64 || d < 4096 || d > (1 << 20) ||
+            (e != 0 && e != 1))
             return RFIM_ERR_INVALID_ARG;
         out->u8_tile_cap = (int)a;
         out->f32_lds = (size_t)b;
         out->f32_tile_cap = (int)c;
         out->u8_lds = (size_t)d;
+        out->u8_sched = (int)e;
         return RFIM_OK;
     }
     return RFIM_ERR_UNSUPPORTED;
@@ -133,15 +140,15 @@ rfim_status tune_cache_store(const char* path, const rfim_beam* shapes, int32_t 
     }
     char buf[256];
     std::snprintf(buf, sizeof buf,
-                  "\"u8_tile_cap\": %d, \"f32_lds\": %zu, \"f32_tile_cap\": %d, \"u8_lds\": %zu, \"ms\": %.6f, "
-                  "\"candidates\": %zu, \"table\": [",
-                  p.u8_tile_cap, p.f32_lds, p.f32_tile_cap, p.u8_lds, ms, table.size());
+                  "\"u8_tile_cap\": %d, \"f32_lds\": %zu, \"f32_tile_cap\": %d, \"u8_lds\": %zu, "
+                  "\"u8_sched\": %d, \"ms\": %.6f, \"candidates\": %zu, \"table\": [",
+                  p.u8_tile_cap, p.f32_lds, p.f32_tile_cap, p.u8_lds, p.u8_sched, ms, table.size());
     std::string e = pre + buf;
-    // table rows: [u8 tile cap, u8 LDS, f32 LDS, f32 tile cap, ms per run]
+    // table rows: [u8 tile cap, u8 LDS, u8 schedule, f32 LDS, f32 tile cap, ms per run]
     for (size_t i = 0; i < table.size(); i++) {
         const TuneRow& r = table[i];
-        std::snprintf(buf, sizeof buf, "%s[%d, %zu, %zu, %d, %.6f]", i ? ", " : "", r.p.u8_tile_cap, r.p.u8_lds,
-                      r.p.f32_lds, r.p.f32_tile_cap, r.ms);
+        std::snprintf(buf, sizeof buf, "%s[%d, %zu, %d, %zu, %d, %.6f]", i ? ", " : "", r.p.u8_tile_cap,
+                      r.p.u8_lds, r.p.u8_sched, r.p.f32_lds, r.p.f32_tile_cap, r.ms);
         e += buf;
     }
     e += "]}";
@@ -244,28 +251,31 @@ using namespace rfim;
 extern "C" {
 
 rfim_status rfim_tune_lookup(const char* path, const rfim_beam* shapes, int32_t nbeams, const rfim_step* steps,
-                             int32_t nsteps, int64_t* out4) {
-    if (!path || !shapes || nbeams < 1 || !steps || nsteps < 1 || !out4) return RFIM_ERR_INVALID_ARG;
+                             int32_t nsteps, int64_t* params) {
+    if (!path || !shapes || nbeams < 1 || !steps || nsteps < 1 || !params) return RFIM_ERR_INVALID_ARG;
     TuneParams p;
     const rfim_status st = tune_cache_lookup(path, shapes, nbeams, steps, nsteps, &p);
     if (st != RFIM_OK) return st;
-    out4[0] = p.u8_tile_cap;
-    out4[1] = (int64_t)p.f32_lds;
-    out4[2] = p.f32_tile_cap;
-    out4[3] = (int64_t)p.u8_lds;
+    params[0] = p.u8_tile_cap;
+    params[1] = (int64_t)p.f32_lds;
+    params[2] = p.f32_tile_cap;
+    params[3] = (int64_t)p.u8_lds;
+    params[4] = p.u8_sched;
     return RFIM_OK;
 }
 
 rfim_status rfim_tune_store(const char* path, const rfim_beam* shapes, int32_t nbeams, const rfim_step* steps,
-                            int32_t nsteps, const int64_t* params4, double ms) {
-    if (!path || !shapes || nbeams < 1 || !steps || nsteps < 1 || !params4) return RFIM_ERR_INVALID_ARG;
+                            int32_t nsteps, const int64_t* params, double ms) {
+    if (!path || !shapes || nbeams < 1 || !steps || nsteps < 1 || !params) return RFIM_ERR_INVALID_ARG;
     TuneParams p;
-    p.u8_tile_cap = (int)params4[0];
-    p.f32_lds = (size_t)params4[1];
-    p.f32_tile_cap = (int)params4[2];
-    p.u8_lds = (size_t)params4[3];
+    p.u8_tile_cap = (int)params[0];
+    p.f32_lds = (size_t)params[1];
+    p.f32_tile_cap = (int)params[2];
+    p.u8_lds = (size_t)params[3];
+    p.u8_sched = (int)params[4];
     if (p.u8_tile_cap < 4 || p.u8_tile_cap > 64 || p.f32_lds < 1024 || p.f32_lds > (1u << 20) ||
-        p.f32_tile_cap < 4 || p.f32_tile_cap > 64 || p.u8_lds < 4096 || p.u8_lds > (1u << 20))
+        p.f32_tile_cap < 4 || p.f32_tile_cap > 64 || p.u8_lds < 4096 || p.u8_lds > (1u << 20) ||
+        (p.u8_sched != 0 && p.u8_sched != 1))
         return RFIM_ERR_INVALID_ARG;
     return tune_cache_store(path, shapes, nbeams, steps, nsteps, p, ms, {});
 }
@@ -323,24 +333,28 @@ rfim_status rfim_autotune(const rfim_beam* shapes, int32_t nbeams, const rfim_st
     cands.push_back(def);
     const int u8caps[] = {16, 32, 64};
     const size_t u8lds[] = {51200, 102400};
+    const int u8sched[] = {0, 1};
     const size_t f32lds[] = {40960, 81920, 163840};
     const int f32caps[] = {8, 64};
     for (int a : u8caps)
         for (size_t ul : u8lds)
-            for (size_t l : f32lds)
-                for (int c : f32caps) {
-                    if (!any_u8 && (a != def.u8_tile_cap || ul != def.u8_lds)) continue;
-                    if (!any_f32 && (l != def.f32_lds || c != def.f32_tile_cap)) continue;
-                    TuneParams p;
-                    p.u8_tile_cap = a;
-                    p.u8_lds = ul;
-                    p.f32_lds = l;
-                    p.f32_tile_cap = c;
-                    if (p.u8_tile_cap == def.u8_tile_cap && p.u8_lds == def.u8_lds && p.f32_lds == def.f32_lds &&
-                        p.f32_tile_cap == def.f32_tile_cap)
-                        continue;
-                    cands.push_back(p);
-                }
+            for (int sc : u8sched)
+                for (size_t l : f32lds)
+                    for (int c : f32caps) {
+                        if (!any_u8 && (a != def.u8_tile_cap || ul != def.u8_lds || sc != def.u8_sched)) continue;
+                        if (!any_f32 && (l != def.f32_lds || c != def.f32_tile_cap)) continue;
+                        TuneParams p;
+                        p.u8_tile_cap = a;
+                        p.u8_lds = ul;
+                        p.u8_sched = sc;
+                        p.f32_lds = l;
+                        p.f32_tile_cap = c;
+                        if (p.u8_tile_cap == def.u8_tile_cap && p.u8_lds == def.u8_lds &&
+                            p.u8_sched == def.u8_sched && p.f32_lds == def.f32_lds &&
+                            p.f32_tile_cap == def.f32_tile_cap)
+                            continue;
+                        cands.push_back(p);
+                    }
 
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) st = RFIM_ERR_DEVICE;
@@ -379,10 +393,10 @@ rfim_status rfim_autotune(const rfim_beam* shapes, int32_t nbeams, const rfim_st
                 st = RFIM_ERR_DEVICE;
             if (st == RFIM_OK && diff != 0) {
                 std::fprintf(stderr,
-                             "rfim_autotune: candidate %zu (u8 tile cap %d, u8 LDS %zu, f32 LDS %zu, f32 tile cap %d) "
-                             "differs from the default configuration in %llu bytes\n",
-                             ci, cands[ci].u8_tile_cap, cands[ci].u8_lds, cands[ci].f32_lds, cands[ci].f32_tile_cap,
-                             diff);
+                             "rfim_autotune: candidate %zu (u8 tile cap %d, u8 LDS %zu, u8 schedule %d, f32 LDS %zu, "
+                             "f32 tile cap %d) differs from the default configuration in %llu bytes\n",
+                             ci, cands[ci].u8_tile_cap, cands[ci].u8_lds, cands[ci].u8_sched, cands[ci].f32_lds,
+                             cands[ci].f32_tile_cap, diff);
                 st = RFIM_ERR_MISMATCH;
             }
         }

@@ -248,27 +248,30 @@ __device__ bool td_decide(const Segment& seg, uint64_t n, uint32_t hv[4], uint64
     return true;
 }
 
-__global__ __launch_bounds__(kBlock) void k_td_rows_u8(const DevBeam* __restrict__ beams,
-                                                       int nbeams, int64_t total_rows, Segment seg,
-                                                       uint32_t* __restrict__ rec,
-                                                       unsigned long long* __restrict__ counts,
-                                                       int count_stride) {
-    __shared__ uint32_t hist_all[kRowsPerWG][kHistCopies * kHistPitch];
-    __shared__ int s_lo_all[kRowsPerWG][kMaxSteps], s_hi_all[kRowsPerWG][kMaxSteps],
-        s_r_all[kRowsPerWG][kMaxSteps];
-    __shared__ unsigned long long s_mv_all[kRowsPerWG][kMaxSteps];
+// LDS of one TD row group (one row per wave)
+struct TdShared {
+    uint32_t hist[kRowsPerWG][kHistCopies * kHistPitch];
+    int lo[kRowsPerWG][kMaxSteps], hi[kRowsPerWG][kMaxSteps], r[kRowsPerWG][kMaxSteps];
+    unsigned long long mv[kRowsPerWG][kMaxSteps];
+    int beam[kRowsPerWG];
+};
 
-    __shared__ int s_beam[kRowsPerWG];
+// Rows g0 .. g0 + kRowsPerWG - 1 of a launch's row space, wave w on row
+// g0 + w; rows at or past `row_end` are skipped.  Called by every thread of
+// the work-group.
+__device__ __attribute__((always_inline)) inline void td_row_group(const DevBeam* __restrict__ beams, int nbeams, int64_t g0, int64_t row_end,
+                                    const Segment& seg, uint32_t* __restrict__ rec,
+                                    unsigned long long* __restrict__ counts, int count_stride, TdShared& sh) {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int64_t g = (int64_t)blockIdx.x * kRowsPerWG + wave;
+    const int64_t g = g0 + wave;
     // waves past the last row skip the row work but still reach the
     // work-group barrier of the flag counts below
-    if (g < total_rows) {
-        unsigned long long* s_mv = s_mv_all[wave];
-        uint32_t* hist = hist_all[wave];
-        int* s_lo = s_lo_all[wave];
-        int* s_hi = s_hi_all[wave];
-        int* s_r = s_r_all[wave];
+    if (g < row_end) {
+        unsigned long long* s_mv = sh.mv[wave];
+        uint32_t* hist = sh.hist[wave];
+        int* s_lo = sh.lo[wave];
+        int* s_hi = sh.hi[wave];
+        int* s_r = sh.r[wave];
         const int b = find_beam_by_row(beams, nbeams, g);
         const DevBeam& bm = beams[b];
         const int64_t c = g - bm.row0;
@@ -340,8 +343,8 @@ __global__ __launch_bounds__(kBlock) void k_td_rows_u8(const DevBeam* __restrict
             }
             rec[g * seg.n_td + j] = (uint32_t)L | ((uint32_t)H << 8) | ((uint32_t)val << 16) | (f << 24);
         }
-        if (lane == 0) s_beam[wave] = bm.cidx;
-    }   // g < total_rows
+        if (lane == 0) sh.beam[wave] = bm.cidx;
+    }   // g < row_end
 
     // Flag counts.  Every row of a beam adds to the same few counters, and
     // one atomic per row and step left the kernel waiting on those atomics
@@ -351,21 +354,30 @@ __global__ __launch_bounds__(kBlock) void k_td_rows_u8(const DevBeam* __restrict
         __syncthreads();
         const int j = threadIdx.x;
         if (j < seg.n_td) {
-            const int64_t g0 = (int64_t)blockIdx.x * kRowsPerWG;
-            const int nw = (int)min((int64_t)kRowsPerWG, total_rows - g0);
-            int cb = s_beam[0];
+            const int nw = (int)min((int64_t)kRowsPerWG, row_end - g0);
+            int cb = sh.beam[0];
             unsigned long long sum = 0;
             for (int w = 0; w < nw; w++) {
-                if (s_beam[w] != cb) {
+                if (sh.beam[w] != cb) {
                     if (sum) atomicAdd(&counts[(int64_t)cb * count_stride + seg.td[j].ci], sum);
-                    cb = s_beam[w];
+                    cb = sh.beam[w];
                     sum = 0;
                 }
-                sum += s_mv_all[w][j];
+                sum += sh.mv[w][j];
             }
             if (sum) atomicAdd(&counts[(int64_t)cb * count_stride + seg.td[j].ci], sum);
         }
     }
+}
+
+
+__global__ __launch_bounds__(kBlock) void k_td_rows_u8(const DevBeam* __restrict__ beams,
+                                                       int nbeams, int64_t total_rows, Segment seg,
+                                                       uint32_t* __restrict__ rec,
+                                                       unsigned long long* __restrict__ counts,
+                                                       int count_stride) {
+    __shared__ TdShared sh;
+    td_row_group(beams, nbeams, (int64_t)blockIdx.x * kRowsPerWG, total_rows, seg, rec, counts, count_stride, sh);
 }
 
 namespace {
@@ -1114,22 +1126,25 @@ __device__ inline void fd_steps_b32(const TileCtx& k, const Segment& seg, uint8_
     }
 }
 
-// One work-group per (beam, time tile); work-groups are handed out so that
-// each XCD gets a contiguous range of tiles.
-template <bool VEC>
-__global__ __launch_bounds__(kBlock) void k_fused_u8(const DevBeam* __restrict__ beams, int nbeams,
-                                                     int64_t total_tiles, Segment seg,
-                                                     const uint32_t* __restrict__ rec,
-                                                     unsigned long long* __restrict__ counts,
-                                                     int count_stride) {
-    extern __shared__ __align__(16) uint8_t lds[];
-    __shared__ uint32_t exc_pos[kExcCap];   // (row << 8) | dword index in the tile
-    __shared__ uint32_t exc_n;
-    __shared__ unsigned long long s_cnt[kMaxSteps];
-    __shared__ uint32_t s_z[64];             // FD threshold per time sample of the tile
+// Static LDS of one fused tile besides the tile itself
+struct FusedShared {
+    uint32_t exc_pos[kExcCap];   // (row << 8) | dword index in the tile
+    uint32_t exc_n;
+    unsigned long long s_cnt[kMaxSteps];
+    uint32_t s_z[64];            // FD threshold per time sample of the tile
+};
 
+// Tile g of a launch's tile space, by the whole work-group; lds holds the
+// [Tt][Cp] tile (and its flag tile).
+template <bool VEC>
+__device__ __attribute__((always_inline)) inline void fused_tile(const DevBeam* __restrict__ beams, int nbeams, int64_t g, const Segment& seg,
+                                  const uint32_t* __restrict__ rec, unsigned long long* __restrict__ counts,
+                                  int count_stride, uint8_t* lds, FusedShared& fs) {
+    uint32_t* exc_pos = fs.exc_pos;
+    uint32_t& exc_n = fs.exc_n;
+    unsigned long long* s_cnt = fs.s_cnt;
+    uint32_t* s_z = fs.s_z;
     const int tid = threadIdx.x;
-    const int64_t g = xcd_remap(blockIdx.x, total_tiles);
     const int b = find_beam_by_tile(beams, nbeams, g);
     const DevBeam& bm = beams[b];
     TileCtx k;
@@ -1292,6 +1307,134 @@ __global__ __launch_bounds__(kBlock) void k_fused_u8(const DevBeam* __restrict__
     }
     if (counts && seg.n_fd > 0 && tid < seg.n_fd && s_cnt[tid])
         atomicAdd(&counts[(int64_t)bm.cidx * count_stride + seg.fd[tid].ci], s_cnt[tid]);
+}
+
+// One work-group per (beam, time tile); work-groups are handed out so that
+// each XCD gets a contiguous range of tiles.
+template <bool VEC>
+__global__ __launch_bounds__(kBlock) void k_fused_u8(const DevBeam* __restrict__ beams, int nbeams,
+                                                     int64_t total_tiles, Segment seg,
+                                                     const uint32_t* __restrict__ rec,
+                                                     unsigned long long* __restrict__ counts,
+                                                     int count_stride) {
+    extern __shared__ __align__(16) uint8_t lds[];
+    __shared__ FusedShared fs;
+    fused_tile<VEC>(beams, nbeams, xcd_remap(blockIdx.x, total_tiles), seg, rec, counts, count_stride, lds, fs);
+}
+
+// ---------------------------------------------------------------------------
+// Persistent beam-major schedule: the TD pass and the fused pass of a run in
+// one launch.  Work items are ordered by beam and, within a beam, its TD row
+// groups come before its tiles, so a beam's second read follows its first
+// closely enough to be served from the Infinity Cache.  The beams are dealt to
+// kPersistQueues queues (balanced by item count on the host); work-group i
+// takes items from queue i mod kPersistQueues, the XCD the hardware deals it
+// to, so a beam's records stay in one XCD's L2, and moves on to the other
+// queues when its own is empty, so every item is taken whatever the mapping.
+// A tile waits until every row group of its beam is done (a per-beam counter,
+// released after the group's records are written and acquired before they are
+// read, once per beam and work-group).  The wait always ends: those row groups
+// were all taken earlier, by running work-groups that never wait.  It is
+// bounded anyway: past spin_limit polls the work-group sets the error word
+// and stops taking items, and the host reports it.  wait_extra (0 in use) is
+// added to the count a tile waits for: a test sets it to make every wait
+// run out on purpose.  Both bodies inlined into one kernel need more
+// registers than either alone; the fused pass's LDS already caps a CU at three
+// work-groups (three waves per SIMD), which the register budget keeps.
+template <bool VEC>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) void k_persist_u8(
+    const DevBeam* __restrict__ beams, int nbeams, PersistQueues qs, Segment seg, uint32_t* __restrict__ rec,
+    unsigned long long* __restrict__ counts, int count_stride, unsigned* __restrict__ ctl, uint32_t spin_limit,
+    uint32_t wait_extra) {
+    extern __shared__ __align__(16) uint8_t lds[];
+    __shared__ FusedShared fs;
+    __shared__ int64_t s_item;
+    __shared__ int s_go;
+    TdShared& tsh = *reinterpret_cast<TdShared*>(lds);   // the tile's LDS, reused by row groups
+    unsigned* next = ctl;                                 // [kPersistQueues]
+    unsigned* err = ctl + kPersistQueues;
+    unsigned* done = ctl + kPersistQueues + 1;            // [nbeams]
+    const int q0 = (int)(blockIdx.x % kPersistQueues);
+    int acquired = -1;   // beam whose row groups this work-group has seen completed
+    for (int qi = 0; qi < kPersistQueues;) {
+        const int q = (q0 + qi) % kPersistQueues;
+        __syncthreads();   // the previous item is done with the LDS
+        if (threadIdx.x == 0) {
+            const int64_t n = qs.base[q + 1] - qs.base[q];
+            const int64_t k = n > 0 ? (int64_t)atomicAdd(&next[q], 1u) : n;
+            s_item = k < n ? qs.base[q] + k : -1;
+        }
+        __syncthreads();
+        const int64_t it = s_item;
+        if (it < 0) {   // this queue is empty: the next one
+            qi++;
+            continue;
+        }
+        int lo = 0, hi = nbeams - 1;   // the beam: last with item0 <= it
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (beams[mid].item0 <= it) lo = mid; else hi = mid - 1;
+        }
+        const DevBeam& bm = beams[lo];
+        const int64_t local = it - bm.item0;
+        const int64_t ntd = seg.n_td > 0 ? (bm.C + kRowsPerWG - 1) / kRowsPerWG : 0;
+        if (local < ntd) {
+            td_row_group(beams, nbeams, bm.row0 + local * kRowsPerWG, bm.row0 + bm.C, seg, rec, counts,
+                         count_stride, tsh);
+            __syncthreads();   // every wave's records are written (work-group scope)
+            if (threadIdx.x == 0) __hip_atomic_fetch_add(&done[lo], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            continue;
+        }
+        if (ntd > 0 && acquired != lo) {
+            if (threadIdx.x == 0) {
+                int ok = 0;
+                for (uint32_t n = 0;; n++) {
+                    if (__hip_atomic_load(&done[lo], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) >=
+                        (unsigned)ntd + wait_extra) {
+                        ok = 1;
+                        break;
+                    }
+                    if (n >= spin_limit) break;
+                    __builtin_amdgcn_s_sleep(4);
+                }
+                if (!ok) atomicOr(err, 1u);
+                s_go = ok;
+            }
+            __syncthreads();
+            if (!s_go) break;
+            acquired = lo;
+        }
+        fused_tile<VEC>(beams, nbeams, bm.tile0 + (local - ntd), seg, rec, counts, count_stride, lds, fs);
+    }
+}
+
+size_t td_group_lds_bytes() { return sizeof(TdShared); }
+
+int persist_u8_grid(size_t lds_bytes, bool vec) {
+    int dev = 0, cus = 0, per = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+        cus = 256;
+    const hipError_t e = vec ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_persist_u8<true>, kBlock, lds_bytes)
+                             : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_persist_u8<false>, kBlock, lds_bytes);
+    if (e != hipSuccess || per <= 0) per = 1;
+    return cus * per;
+}
+
+hipError_t launch_persist_u8(const DevBeam* d_beams, int nbeams, const PersistQueues& qs, const Segment& seg,
+                             uint32_t* d_rec, size_t lds_bytes, bool vec, unsigned long long* d_counts,
+                             int count_stride, unsigned* ctl, uint32_t spin_limit, uint32_t wait_extra, int grid,
+                             hipStream_t s) {
+    const int64_t total_items = qs.base[kPersistQueues];
+    if (total_items <= 0) return hipSuccess;
+    grid = (int)std::min<int64_t>(grid, total_items);
+    if (vec)
+        hipLaunchKernelGGL(k_persist_u8<true>, dim3(grid), dim3(kBlock), lds_bytes, s, d_beams, nbeams, qs, seg,
+                           d_rec, d_counts, count_stride, ctl, spin_limit, wait_extra);
+    else
+        hipLaunchKernelGGL(k_persist_u8<false>, dim3(grid), dim3(kBlock), lds_bytes, s, d_beams, nbeams, qs, seg,
+                           d_rec, d_counts, count_stride, ctl, spin_limit, wait_extra);
+    return hipGetLastError();
 }
 
 hipError_t launch_td_rows_u8(const DevBeam* d_beams, int nbeams, int64_t total_rows,
