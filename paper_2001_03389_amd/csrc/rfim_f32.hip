@@ -252,12 +252,23 @@ __device__ inline void td_row_f32(const DevBeam& bm, int64_t c, const Segment& s
     // rank floor((n-1)/2)); known_med says m is current.
     bool known_med = false;
     float cur_med = 0.0f;
+    // First window: after the first step the exact sums change only by the
+    // replaced samples, so each lane accumulates (r - x) and (r^2 - x^2) of the
+    // samples it replaces (integers in units of the window) and the next step
+    // adds those deltas to the running totals wave 0 keeps.
+    int64_t dS = 0;
+    u128 dQ = 0;          // two's complement: the deltas may be negative
+    i128 St_run = 0;      // wave 0: running exact sums of the first window
+    u128 Qt_run = 0;
     for (int j = 0; j < seg.n_td && !bad && !to_two; j++) {
         const SegStep& st = seg.td[j];
         // exact window sums (both windows when the row has values below the first)
         int64_t S = 0, S1 = 0;
         u128 Q = 0, Q1 = 0;
-        if (!tiny) {
+        if (!tiny && j > 0) {
+            S = dS;
+            Q = dQ;
+        } else if (!tiny) {
 #pragma unroll
             for (int i0 = 0; i0 < VPT; i0 += 32) {
                 WinAcc w{0.0, 0.0, 0.0};
@@ -316,6 +327,14 @@ __device__ inline void td_row_f32(const DevBeam& bm, int64_t c, const Segment& s
                 St1 += s_S1[w];
                 Qt1 += ((u128)s_Q1[w][1] << 64) | s_Q1[w][0];
             }
+            if (!TWO) {   // step j > 0: St, Qt are the deltas of step j - 1's replacements
+                if (j > 0) {
+                    St += St_run;
+                    Qt += Qt_run;
+                }
+                St_run = St;
+                Qt_run = Qt;
+            }
             float H, Lo, rm;
             if (!TWO) {
                 const u128 Sa = St < 0 ? (u128)(-St) : (u128)St;
@@ -361,12 +380,22 @@ __device__ inline void td_row_f32(const DevBeam& bm, int64_t c, const Segment& s
         known_med = st.replace == RFIM_REPLACE_MEDIAN && !(med < Lo) && !(med > H);
         cur_med = med;
         uint32_t cnt = 0;
+        const int64_t ra = (int64_t)((double)r * sc);   // r lies in the first window (else the row left it)
+        dS = 0;
+        dQ = 0;
 #pragma unroll
         for (int i = 0; i < VPT; i++) {
             if (i < nv) {
                 const float x = get(i);
                 const bool f = x < Lo || x > H;
-                if (f) set(i, r);
+                if (f) {
+                    set(i, r);
+                    if (!tiny) {
+                        const int64_t a = (int64_t)((double)x * sc);
+                        dS += ra - a;
+                        dQ += (u128)((i128)ra * ra) - (u128)((i128)a * a);
+                    }
+                }
                 cnt += f ? 1u : 0u;
             }
         }
@@ -507,6 +536,9 @@ __device__ inline int fd_column_f32(float (&x)[BPL][B], uint32_t (&fw)[BPL][B / 
             u128 V = 0;
 #pragma unroll
             for (int kk = 0; kk < BPL; kk++) {
+                // recomputed every step: replacements reach most waves, and an
+                // update by the replaced samples costs more (128-bit squares
+                // under divergence) than one exact pass over the bin
                 int64_t Sb = 0;
                 u128 Qb = 0;
 #pragma unroll
