@@ -125,8 +125,8 @@ rfim_status rfim_pipeline_run(const rfim_beam* beams, int32_t nbeams, const rfim
  * rfim_pipeline_run(beams, nbeams, steps, nsteps, NULL, stream), with the
  * default kernel configuration and no flag counts.  Returns
  * RFIM_ERR_SCRATCH, before enqueuing anything, when the call needs more
- * (per TD step 4 bytes per uint8 row and 16 per float32 row; 16 bytes per
- * float32 row and per float32 time sample; about 100 bytes of launch table
+ * (per TD step 4 bytes per uint8 row and 16 per float32 row; 24 bytes per
+ * float32 row and 16 per float32 time sample; about 100 bytes of launch table
  * per beam and run: 16 float32 beams of 4096 x 65536 need about 22 MB).  Every call on a
  * GPU uses that GPU's one array and leaves its contents behind: calls that
  * overlap on one GPU (two streams, two host threads) race and must be
@@ -160,8 +160,10 @@ rfim_status rfim_plan_replay_on(rfim_plan* plan, const rfim_beam* beams, int32_t
 
 /* Auto-tuner (Section III: parameters tuned per setup and platform, the
  * configurations saved for production).  Times every candidate kernel
- * configuration (uint8 tile cap and LDS budget, uint8 schedule, float32 LDS
- * budget and tile cap) for these shapes and steps on freshly allocated beams filled
+ * configuration (uint8 tile cap and LDS budget, uint8 schedule, uint8 TD rows
+ * per work-group, float32 LDS budget and tile cap: the uint8 axes on the
+ * default float32 setting, then the float32 axes on the best uint8 one) for
+ * these shapes and steps on freshly allocated beams filled
  * on the device with a deterministic pattern shaped like channelised
  * telescope data (per-channel level and spread, narrow-band channels,
  * broadband impulses), and stores the fastest in the JSON cache file
@@ -177,13 +179,14 @@ rfim_status rfim_autotune(const rfim_beam* shapes, int32_t nbeams, const rfim_st
                           const char* tune_cache_path, void* stream, double* best_ms);
 
 /* Number of tuning parameters of a cache entry. */
-#define RFIM_TUNE_NPARAMS 5
+#define RFIM_TUNE_NPARAMS 6
 
 /* Tuning-cache access without a GPU: rfim_tune_lookup fills
  * params[RFIM_TUNE_NPARAMS] = {uint8 tile cap (samples), float32 LDS budget
  * (bytes), float32 tile cap, uint8 LDS budget (bytes), uint8 schedule (0 = a
  * TD pass then a fused pass over all beams of the call, 1 = one persistent
- * beam-major launch per run of [TD][FD] steps)} for the key of these shapes
+ * beam-major launch per run of [TD][FD] steps), uint8 TD rows per work-group
+ * (2, 4 or 8)} for the key of these shapes
  * and steps (RFIM_ERR_UNSUPPORTED: no entry or no file); rfim_tune_store adds
  * or replaces that entry (RFIM_ERR_INVALID_ARG for values out of range). */
 rfim_status rfim_tune_lookup(const char* path, const rfim_beam* shapes, int32_t nbeams, const rfim_step* steps,

@@ -244,13 +244,13 @@ def _shape_array(shapes):
     return arr
 
 
-RFIM_TUNE_NPARAMS = 5
+RFIM_TUNE_NPARAMS = 6
 
 
 def tune_lookup(path: str, shapes: Sequence[rfim_beam], steps: Sequence):
     """(uint8 tile cap, float32 LDS bytes, float32 tile cap, uint8 LDS bytes,
-    uint8 schedule) stored in the tuning cache for these shapes and steps, or
-    None (rfim_tune_lookup)."""
+    uint8 schedule, uint8 TD rows per work-group) stored in the tuning cache
+    for these shapes and steps, or None (rfim_tune_lookup)."""
     out = (ctypes.c_int64 * RFIM_TUNE_NPARAMS)()
     rc = lib().rfim_tune_lookup(path.encode(), _shape_array(shapes), len(shapes), make_steps(steps),
                                 len(steps), out)
@@ -263,7 +263,7 @@ def tune_lookup(path: str, shapes: Sequence[rfim_beam], steps: Sequence):
 def tune_store(path: str, shapes: Sequence[rfim_beam], steps: Sequence, params, ms: float = 0.0) -> None:
     """Adds or replaces the cache entry of these shapes and steps (rfim_tune_store)."""
     vals = [int(v) for v in params]
-    defaults = [64, 81920, 64, 51200, 0]   # uint8 LDS budget and schedule may be left out
+    defaults = [64, 81920, 64, 51200, 0, 4]   # the uint8 LDS budget, schedule and TD rows may be left out
     if not 3 <= len(vals) <= RFIM_TUNE_NPARAMS:
         raise ValueError(f"3 to {RFIM_TUNE_NPARAMS} tuning parameters expected")
     vals += defaults[len(vals):]

@@ -51,7 +51,8 @@ def build(verbose: bool = False) -> str:
         if verbose and errs.strip():
             print(errs, file=sys.stderr)
     tmp = LIB + ".tmp"
-    cmd = [hipcc, "-shared", "-fPIC", f"--offload-arch={ARCH}", *[o for _, o, _, _ in results], "-o", tmp]
+    # -z defs: a symbol no object defines fails the link instead of the load
+    cmd = [hipcc, "-shared", "-fPIC", "-Wl,-z,defs", f"--offload-arch={ARCH}", *[o for _, o, _, _ in results], "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed ({r.returncode}):\n{_filtered(r.stderr)}")

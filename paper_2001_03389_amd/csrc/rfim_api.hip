@@ -357,7 +357,7 @@ struct LaunchPlan {
     int64_t f32_rows = 0, f32_cols = 0, f32_maxC = 0;
     // workspace layout (byte offsets)
     size_t off_u8rec = 0, off_f32rec = 0, off_wide = 0, off_tditems = 0, off_fditems = 0;
-    size_t off_tdtiny = 0, off_fdtiny = 0;
+    size_t off_tdtiny = 0, off_fdtiny = 0, off_f32fast = 0;
     size_t count_bytes = 0, work_bytes = 0;
     // uint8 persistent schedule: control words [next item per queue, error,
     // done per uint8 beam] (zeroed before each launch), the sticky error word,
@@ -496,7 +496,8 @@ rfim_status make_launch_plan(const rfim_beam* beams, int32_t nbeams, const rfim_
     lp->off_fditems = lp->off_tditems + al((size_t)lp->f32_rows * 8);
     lp->off_tdtiny = lp->off_fditems + al((size_t)lp->f32_cols * 8);
     lp->off_fdtiny = lp->off_tdtiny + al((size_t)lp->f32_rows * 8);
-    lp->work_bytes = lp->off_fdtiny + al((size_t)lp->f32_cols * 8);
+    lp->off_f32fast = lp->off_fdtiny + al((size_t)lp->f32_cols * 8);
+    lp->work_bytes = lp->off_f32fast + al((size_t)lp->f32_rows * 8);
     // the sticky error word of the persistent schedule (zeroed with the workspace)
     lp->off_err = lp->work_bytes;
     lp->work_bytes += 256;
@@ -527,6 +528,7 @@ rfim_status dev_err(hipError_t e) {
 // ---------------------------------------------------------------------------
 enum Op {
     OP_ZERO_COUNTS, OP_TD_U8, OP_FUSED_U8, OP_PERSIST_U8, OP_ZERO_WIDE, OP_TD_F32, OP_TD_TWO, OP_LIST_ALL, OP_TD_WIDE,
+    OP_TD_COMPOSE,
     OP_FUSED_F32, OP_FD_TWO, OP_FD_WIDE
 };
 
@@ -736,6 +738,11 @@ void build_f32(const rfim_beam* beams, const LaunchPlan& lp, Program& pg) {
             W.nbeams = nf;
             W.a = (int)std::min<int64_t>(rows, 512);
             pg.launches.push_back(W);
+            Launch K;   // composite records of every float32 row of the run
+            K.op = OP_TD_COMPOSE;
+            K.seg = sidx;
+            K.total = rows;
+            pg.launches.push_back(K);
         }
         for (auto& fsh : fd_shapes) {
             const int table = (int)pg.blob.size();
@@ -824,6 +831,7 @@ rfim_status enqueue(const Program& pg, const LaunchPlan& lp, const DevBeam* d_bl
     unsigned* tiny_fd_n = (unsigned*)(wbase + lp.off_wide + 24);
     int2* td_tiny = (int2*)(wbase + lp.off_tdtiny);
     int2* fd_tiny = (int2*)(wbase + lp.off_fdtiny);
+    float2* ffast = (float2*)(wbase + lp.off_f32fast);
     for (const Launch& L : pg.launches) {
         const DevBeam* tab = L.table >= 0 ? d_blob + L.table : nullptr;
         const Segment& seg = pg.segs[L.seg >= 0 ? L.seg : 0];
@@ -834,7 +842,8 @@ rfim_status enqueue(const Program& pg, const LaunchPlan& lp, const DevBeam* d_bl
                 break;
             case OP_TD_U8:
                 e = timed(RFIM_KERNEL_TD_ROWS_U8, [&] {
-                    return launch_td_rows_u8(tab, L.nbeams, L.total, seg, u8rec, counts, kCountStride, stream);
+                    return launch_td_rows_u8(tab, L.nbeams, L.total, lp.tune.u8_td_rows, seg, u8rec, counts,
+                                             kCountStride, stream);
                 });
                 break;
             case OP_FUSED_U8:
@@ -879,6 +888,9 @@ rfim_status enqueue(const Program& pg, const LaunchPlan& lp, const DevBeam* d_bl
             case OP_LIST_ALL:
                 e = launch_list_all(L.b ? wide_fd_n : wide_td_n, L.b ? fd_items : td_items, L.a, L.total, stream);
                 break;
+            case OP_TD_COMPOSE:
+                e = launch_td_compose_f32(frec, ffast, L.total, seg, stream);
+                break;
             case OP_TD_WIDE:
                 e = timed(RFIM_KERNEL_TD_WIDE_F32, [&] {
                     return launch_td_wide_f32(tab, wide_td_n, td_items, L.a, seg, frec, counts, kCountStride, stream);
@@ -886,7 +898,7 @@ rfim_status enqueue(const Program& pg, const LaunchPlan& lp, const DevBeam* d_bl
                 break;
             case OP_FUSED_F32:
                 e = timed(RFIM_KERNEL_FUSED_F32, [&] {
-                    return launch_fused_f32(tab, L.nbeams, L.total, L.a, L.b, seg, frec, L.lds, tiny_fd_n, fd_tiny,
+                    return launch_fused_f32(tab, L.nbeams, L.total, L.a, L.b, seg, frec, ffast, L.lds, tiny_fd_n, fd_tiny,
                                             wide_fd_n, fd_items, counts, kCountStride, stream);
                 });
                 break;

@@ -16,6 +16,8 @@
 // Rows and time samples that leave the window (values more than 2^-24 below
 // the largest one, or a replacement value that is) go to lists that the wide
 // kernels k_td_wide_f32 / k_fd_wide_f32 finish with big integers.
+#include <algorithm>
+
 #include "rfim_big.h"
 #include "rfim_dev.h"
 
@@ -448,12 +450,14 @@ __global__ __launch_bounds__(1024) void k_td_two_f32(const DevBeam* __restrict__
 namespace {
 
 constexpr int kF32Block = 256;
+constexpr int kF32Exc = 1024;   // TD exceptions listed per fused tile (4 KB: two 78 KB tiles fit a CU)
 
 struct F32Tile {
     const float* in;
     float* out;
     uint8_t* flags;
-    const float4* rec;   // this beam's TD records, [row][n_td]
+    const float4* rec;   // this beam's composite TD records, [row][n_td]
+    const float2* fast;  // this beam's innermost kept interval per row
     int64_t C, T, stride, t0;
     int Tt, Cp, nt, n_td;
 };
@@ -707,17 +711,58 @@ __device__ inline int64_t phys_chan(int64_t c, int B) { return B ? c + (c / B) *
 
 }  // namespace
 
+// Composite TD records of a run, one thread per float32 row, after every TD
+// kernel of the run has written its raw records (Lo_j, H_j, r_j): in place,
+// (Lc_j, Hc_j, v_j, bits_j) with [Lc_j, Hc_j] the intersection of the kept
+// intervals of steps 0..j (a value inside it is untouched through step j),
+// v_j the value a sample first cut at step j ends with (r_j, then replaced
+// again by any later step that cuts it) and bits_j the flag bits it collects;
+// fast[row] = the innermost interval [Lc, Hc] of the last step.
+__global__ void k_td_compose_f32(float4* __restrict__ rec, float2* __restrict__ fast, int64_t rows, Segment seg) {
+    const int n = seg.n_td;
+    for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < rows; r += (int64_t)gridDim.x * blockDim.x) {
+        float4 raw[kMaxSteps];
+        float4* rp = rec + r * n;
+        for (int j = 0; j < n; j++) raw[j] = rp[j];
+        float Lc = -INFINITY, Hc = INFINITY;
+        for (int j = 0; j < n; j++) {
+            Lc = fmaxf(Lc, raw[j].x);
+            Hc = fminf(Hc, raw[j].y);
+            float v = raw[j].z;
+            uint32_t bits = seg.td[j].bit >= 0 ? 1u << seg.td[j].bit : 0u;
+            for (int kk = j + 1; kk < n; kk++) {
+                if (v < raw[kk].x || v > raw[kk].y) {
+                    v = raw[kk].z;
+                    if (seg.td[kk].bit >= 0) bits |= 1u << seg.td[kk].bit;
+                }
+            }
+            rp[j] = make_float4(Lc, Hc, v, __uint_as_float(bits));
+        }
+        fast[r] = make_float2(Lc, Hc);
+    }
+}
+
+hipError_t launch_td_compose_f32(float4* rec, float2* fast, int64_t rows, const Segment& seg, hipStream_t s) {
+    if (rows <= 0 || seg.n_td == 0) return hipSuccess;
+    const int blocks = (int)std::min<int64_t>((rows + 255) / 256, 2048);
+    hipLaunchKernelGGL(k_td_compose_f32, dim3(blocks), dim3(256), 0, s, rec, fast, rows, seg);
+    return hipGetLastError();
+}
+
 // B = bin size of the fast FD path (0: no fast FD; every time sample of a run
 // with FD steps then goes to the wide list).  BPL = bins per lane.
 template <int B, int BPL>
 __global__ __launch_bounds__(kF32Block) void k_fused_f32(const DevBeam* __restrict__ beams, int nbeams,
                                                          int64_t total_tiles, Segment seg,
                                                          const float4* __restrict__ rec,
+                                                         const float2* __restrict__ fast,
                                                          unsigned* __restrict__ tiny_n, int2* __restrict__ tiny_items,
                                                          unsigned* __restrict__ wide_n, int2* __restrict__ wide_items,
                                                          unsigned long long* __restrict__ counts, int count_stride) {
     extern __shared__ __align__(16) uint8_t lds[];
     __shared__ unsigned long long s_cnt[kMaxSteps];
+    __shared__ uint32_t s_exc[kF32Exc];   // (row << 8) | tile sample of the values a TD step cuts
+    __shared__ uint32_t s_exc_n;
     const int tid = threadIdx.x;
     const int64_t g = xcd_remap(blockIdx.x, total_tiles);
     const int b = find_beam_by_tile(beams, nbeams, g);
@@ -735,38 +780,46 @@ __global__ __launch_bounds__(kF32Block) void k_fused_f32(const DevBeam* __restri
     k.nt = (int)min((int64_t)k.Tt, k.T - k.t0);
     k.n_td = seg.n_td;
     k.rec = rec + bm.rec0 * seg.n_td;
+    k.fast = fast + bm.rec0;
     const bool want_flags = seg.flags_mode != 0 && bm.flags != nullptr;
     const bool or_flags = seg.flags_mode == 2;
     const bool vec = (k.stride & 3) == 0 && (((uintptr_t)k.in | (uintptr_t)k.out) & 15) == 0;
     float* tile = (float*)lds;
     uint8_t* ftile = lds + (size_t)k.Tt * k.Cp * 4;
-    const int TQ = k.Tt >> 2;   // 4-sample quads per tile row
-    const int64_t nitems = k.C * TQ;
+    const int tq_log = __ffs(k.Tt >> 2) - 1;   // 4-sample quads per tile row: a power of two
+    const int TQ = 1 << tq_log;
+    const int nitems = (int)k.C << tq_log;     // below 2^31: C < 2^24, Tt <= 64
     if (tid < kMaxSteps) s_cnt[tid] = 0;
+    if (tid == 0) s_exc_n = 0;
+    __syncthreads();
 
-    // ---- phase 1: rows in, TD records applied, into LDS (B > 0) or straight out.
-    // kB1 items per thread at a time; with at most 4 TD steps their row loads
-    // and every record they need are requested before any is used.
+    // ---- phase 1: rows in, TD applied, into LDS (B > 0) or straight out.
+    // The TD steps' composite records nest, so a value inside the row's
+    // innermost kept interval is untouched by every step: one compare pair per
+    // value.  Values outside it (rare) take the first step whose interval
+    // excludes them: listed in LDS and mapped after the loop by all threads
+    // together (their record loads in flight at once); past the list's
+    // capacity, and when the tile goes straight out, mapped in place.  kB1
+    // items per thread have their row loads and interval loads in flight
+    // together.
     constexpr int kB1 = 4;
-    const bool prefetch = k.n_td <= 4;
-    for (int64_t it0 = tid; it0 < nitems; it0 += kB1 * kF32Block) {
+    for (int it0 = tid; it0 < nitems; it0 += kB1 * kF32Block) {
         float xs[kB1][4];
-        float4 rs[kB1][4];
-        int64_t cs[kB1], ts[kB1];
-        int qs[kB1];
+        float2 fr[kB1];
+        int cs[kB1], qs[kB1];
         bool oks[kB1];
 #pragma unroll
         for (int u = 0; u < kB1; u++) {
-            const int64_t it = it0 + (int64_t)u * kF32Block;
-            const int64_t c = it / TQ;
-            const int q = (int)(it - c * TQ);
+            const int it = it0 + u * kF32Block;
+            const int c = it >> tq_log;
+            const int q = it & (TQ - 1);
             const int64_t t = k.t0 + 4 * q;
             cs[u] = c;
             qs[u] = q;
-            ts[u] = t;
             oks[u] = it < nitems && t < k.T;
+            fr[u] = make_float2(-INFINITY, INFINITY);
             if (!oks[u]) continue;
-            const float* p = k.in + c * k.stride + t;
+            const float* p = k.in + (int64_t)c * k.stride + t;
             if (vec && t + 3 < k.T) {
                 const float4 f = *(const float4*)p;
                 xs[u][0] = f.x;
@@ -777,54 +830,53 @@ __global__ __launch_bounds__(kF32Block) void k_fused_f32(const DevBeam* __restri
 #pragma unroll
                 for (int jj = 0; jj < 4; jj++) xs[u][jj] = t + jj < k.T ? p[jj] : 0.0f;
             }
-            if (prefetch) {
-#pragma unroll
-                for (int jj = 0; jj < 4; jj++)
-                    rs[u][jj] = jj < k.n_td ? k.rec[c * k.n_td + jj] : make_float4(0.f, 0.f, 0.f, 0.f);
-            }
+            if (k.n_td > 0) fr[u] = k.fast[c];
         }
 #pragma unroll
         for (int u = 0; u < kB1; u++) {
             if (!oks[u]) continue;
-            const int64_t c = cs[u];
+            const int c = cs[u];
             const int q = qs[u];
-            const int64_t t = ts[u];
+            const int64_t t = k.t0 + 4 * q;
             float* x = xs[u];
             uint32_t fb[4] = {0u, 0u, 0u, 0u};
-            for (int j = 0; j < k.n_td; j++) {
-                float4 r4;
-                if (prefetch) {
-                    r4 = rs[u][0];
 #pragma unroll
-                    for (int jj = 1; jj < 4; jj++)
-                        if (j == jj) r4 = rs[u][jj];
-                } else {
-                    r4 = k.rec[c * k.n_td + j];
+            for (int uu = 0; uu < 4; uu++) {
+                if (!(x[uu] < fr[u].x || x[uu] > fr[u].y)) continue;
+                if (B > 0) {
+                    const uint32_t slot = atomicAdd(&s_exc_n, 1u);
+                    if (slot < (uint32_t)kF32Exc) {
+                        s_exc[slot] = ((uint32_t)c << 8) | (uint32_t)(4 * q + uu);
+                        continue;   // mapped after the loop
+                    }
                 }
-                const int bit = seg.td[j].bit;
-#pragma unroll
-                for (int uu = 0; uu < 4; uu++) {
-                    const bool f = x[uu] < r4.x || x[uu] > r4.y;
-                    x[uu] = f ? r4.z : x[uu];
-                    if (f && bit >= 0) fb[uu] |= 1u << bit;
+                // the first step whose composite interval excludes x decides
+                const float4* rp = k.rec + (int64_t)c * k.n_td;
+                for (int j = 0; j < k.n_td; j++) {
+                    const float4 r4 = rp[j];
+                    if (x[uu] < r4.x || x[uu] > r4.y) {
+                        x[uu] = r4.z;
+                        fb[uu] = __float_as_uint(r4.w);
+                        break;
+                    }
                 }
             }
             if (want_flags && or_flags) {
-                const uint8_t* fp = k.flags + c * k.stride + t;
+                const uint8_t* fp = k.flags + (int64_t)c * k.stride + t;
 #pragma unroll
                 for (int uu = 0; uu < 4; uu++)
                     if (t + uu < k.T) fb[uu] |= fp[uu];
             }
             if (B > 0) {
-                const int64_t pc = phys_chan(c, B);
+                const int pc = (int)phys_chan(c, B);
 #pragma unroll
-                for (int uu = 0; uu < 4; uu++) tile[(size_t)(4 * q + uu) * k.Cp + pc] = x[uu];
+                for (int uu = 0; uu < 4; uu++) tile[(4 * q + uu) * k.Cp + pc] = x[uu];
                 if (want_flags) {
 #pragma unroll
-                    for (int uu = 0; uu < 4; uu++) ftile[(size_t)(4 * q + uu) * k.C + c] = (uint8_t)fb[uu];
+                    for (int uu = 0; uu < 4; uu++) ftile[(4 * q + uu) * (int)k.C + c] = (uint8_t)fb[uu];
                 }
             } else {
-                float* op = k.out + c * k.stride + t;
+                float* op = k.out + (int64_t)c * k.stride + t;
                 if (vec && t + 3 < k.T) {
                     *(float4*)op = make_float4(x[0], x[1], x[2], x[3]);
                 } else {
@@ -833,12 +885,34 @@ __global__ __launch_bounds__(kF32Block) void k_fused_f32(const DevBeam* __restri
                         if (t + uu < k.T) op[uu] = x[uu];
                 }
                 if (want_flags) {
-                    uint8_t* fp = k.flags + c * k.stride + t;
+                    uint8_t* fp = k.flags + (int64_t)c * k.stride + t;
 #pragma unroll
                     for (int uu = 0; uu < 4; uu++)
                         if (t + uu < k.T) fp[uu] = (uint8_t)fb[uu];
                 }
             }
+        }
+    }
+    if (B > 0 && k.n_td > 0) {
+        __syncthreads();   // the tile and the list are complete
+        const uint32_t ne = min(s_exc_n, (uint32_t)kF32Exc);
+        for (uint32_t e = tid; e < ne; e += kF32Block) {
+            const uint32_t pos = s_exc[e];
+            const int c = (int)(pos >> 8), ts = (int)(pos & 255u);
+            const int pc = (int)phys_chan(c, B);
+            float x = tile[ts * k.Cp + pc];
+            uint32_t bits = 0;
+            const float4* rp = k.rec + (int64_t)c * k.n_td;
+            for (int j = 0; j < k.n_td; j++) {
+                const float4 r4 = rp[j];
+                if (x < r4.x || x > r4.y) {
+                    x = r4.z;
+                    bits = __float_as_uint(r4.w);
+                    break;
+                }
+            }
+            tile[ts * k.Cp + pc] = x;
+            if (want_flags) ftile[ts * (int)k.C + c] |= (uint8_t)bits;
         }
     }
     if (B == 0) {
@@ -861,17 +935,16 @@ __global__ __launch_bounds__(kF32Block) void k_fused_f32(const DevBeam* __restri
     __syncthreads();
 
     // ---- phase 3: tile back to rows
-    const int64_t pcB = B;
-    for (int64_t it = tid; it < nitems; it += kF32Block) {
-        const int64_t c = it / TQ;
-        const int q = (int)(it - c * TQ);
+    for (int it = tid; it < nitems; it += kF32Block) {
+        const int c = it >> tq_log;
+        const int q = it & (TQ - 1);
         const int64_t t = k.t0 + 4 * q;
         if (t >= k.T) continue;
-        const int64_t pc = phys_chan(c, (int)pcB);
+        const int pc = (int)phys_chan(c, B);
         float x[4];
 #pragma unroll
-        for (int u = 0; u < 4; u++) x[u] = tile[(size_t)(4 * q + u) * k.Cp + pc];
-        float* op = k.out + c * k.stride + t;
+        for (int u = 0; u < 4; u++) x[u] = tile[(4 * q + u) * k.Cp + pc];
+        float* op = k.out + (int64_t)c * k.stride + t;
         if (vec && t + 3 < k.T) {
             *(float4*)op = make_float4(x[0], x[1], x[2], x[3]);
         } else {
@@ -880,10 +953,10 @@ __global__ __launch_bounds__(kF32Block) void k_fused_f32(const DevBeam* __restri
                 if (t + u < k.T) op[u] = x[u];
         }
         if (want_flags) {
-            uint8_t* fp = k.flags + c * k.stride + t;
+            uint8_t* fp = k.flags + (int64_t)c * k.stride + t;
 #pragma unroll
             for (int u = 0; u < 4; u++)
-                if (t + u < k.T) fp[u] = ftile[(size_t)(4 * q + u) * k.C + c];
+                if (t + u < k.T) fp[u] = ftile[(4 * q + u) * (int)k.C + c];
         }
     }
     if (counts && seg.n_fd > 0) {
@@ -1208,7 +1281,8 @@ hipError_t launch_td_rows_f32(const DevBeam* d_beams, int nbeams, int64_t total_
 }
 
 hipError_t launch_fused_f32(const DevBeam* d_beams, int nbeams, int64_t total_tiles, int B, int bpl,
-                            const Segment& seg, const float4* rec, size_t lds_bytes, unsigned* tiny_n,
+                            const Segment& seg, const float4* rec, const float2* fast, size_t lds_bytes,
+                            unsigned* tiny_n,
                             int2* tiny_items, unsigned* wide_n, int2* wide_items, unsigned long long* counts,
                             int count_stride, hipStream_t s) {
     if (total_tiles <= 0) return hipSuccess;
@@ -1216,7 +1290,7 @@ hipError_t launch_fused_f32(const DevBeam* d_beams, int nbeams, int64_t total_ti
 #define RFIM_FF(B_, BPL_)                                                                              \
     if (B == B_ && bpl == BPL_) {                                                                      \
         hipLaunchKernelGGL((k_fused_f32<B_, BPL_>), grid, dim3(kF32Block), lds_bytes, s, d_beams, nbeams, \
-                           total_tiles, seg, rec, tiny_n, tiny_items, wide_n, wide_items, counts,      \
+                           total_tiles, seg, rec, fast, tiny_n, tiny_items, wide_n, wide_items, counts, \
                            count_stride);                                                              \
         return hipGetLastError();                                                                      \
     }

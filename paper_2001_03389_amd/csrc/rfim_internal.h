@@ -65,7 +65,8 @@ struct DevBeam {
 
 // Host launchers (defined in the .hip files).  counts (nullable) receives, per
 // beam, the number of samples each step replaced: counts[beam * count_stride + bit].
-hipError_t launch_td_rows_u8(const DevBeam* d_beams, int nbeams, int64_t total_rows,
+// rows_per_wg: 2, 4 or 8 rows (waves) per work-group
+hipError_t launch_td_rows_u8(const DevBeam* d_beams, int nbeams, int64_t total_rows, int rows_per_wg,
                              const Segment& seg, uint32_t* d_rec, unsigned long long* d_counts,
                              int count_stride, hipStream_t s);
 // vec: every FD step's per-lane bin share is a multiple of 16 bytes (see
@@ -94,7 +95,8 @@ hipError_t launch_persist_u8(const DevBeam* d_beams, int nbeams, const PersistQu
 int persist_u8_grid(size_t lds_bytes, bool vec);
 size_t td_group_lds_bytes();
 
-// float32 launchers.  TD records are float4 (Lo, H, r, 0) per row and step;
+// float32 launchers.  TD kernels write float4 records (Lo, H, r, 0) per row
+// and step, which launch_td_compose_f32 turns into composite ones;
 // wide lists hold (float32 beam index, row or time sample) pairs after a
 // counter.  nt x vpt: work-group size and values per lane of the TD kernel
 // (nt * vpt >= T).  B, bpl: fast FD bin size (0 = none) and bins per lane.
@@ -104,8 +106,12 @@ hipError_t launch_td_rows_f32(const DevBeam* d_beams, int nbeams, int64_t total_
 hipError_t launch_td_two_f32(const DevBeam* d_all, const unsigned* tiny_n, const int2* tiny_items, int grid,
                              const Segment& seg, float4* rec, unsigned* wide_n, int2* wide_items,
                              unsigned long long* counts, int count_stride, hipStream_t s);
+// composite TD records (in place) and each row's innermost kept interval
+// (fast), after every TD kernel of the run
+hipError_t launch_td_compose_f32(float4* rec, float2* fast, int64_t rows, const Segment& seg, hipStream_t s);
 hipError_t launch_fused_f32(const DevBeam* d_beams, int nbeams, int64_t total_tiles, int B, int bpl,
-                            const Segment& seg, const float4* rec, size_t lds_bytes, unsigned* tiny_n,
+                            const Segment& seg, const float4* rec, const float2* fast, size_t lds_bytes,
+                            unsigned* tiny_n,
                             int2* tiny_items, unsigned* wide_n, int2* wide_items, unsigned long long* counts,
                             int count_stride, hipStream_t s);
 // time samples listed by the fused kernel for both windows; the all-beam

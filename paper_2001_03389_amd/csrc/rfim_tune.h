@@ -18,10 +18,11 @@ struct TuneParams {
     size_t u8_lds = 51200;       // LDS budget of a uint8 fused work-group (bytes)
     int u8_sched = 0;            // uint8 schedule: 0 = TD pass then fused pass over the whole call,
                                  // 1 = one persistent beam-major launch per run
+    int u8_td_rows = 4;          // uint8 TD pass: rows (waves) per work-group, 2, 4 or 8
 };
 
-// Defaults; RFIM_TILE_T, RFIM_F32_LDS, RFIM_F32_TILE_T, RFIM_U8_LDS and RFIM_U8_SCHED in the
-// environment override them (experiments).
+// Defaults; RFIM_TILE_T, RFIM_F32_LDS, RFIM_F32_TILE_T, RFIM_U8_LDS, RFIM_U8_SCHED and
+// RFIM_U8_TD_ROWS in the environment override them (experiments).
 TuneParams default_tune();
 
 // Cache key of an ordered list of beam shapes (dtype, nchan, nsamp,

@@ -13,8 +13,9 @@
 //
 // Cache file: one JSON object; each entry sits on its own line,
 //   "<key>": {"u8_tile_cap": 64, "f32_lds": 81920, "f32_tile_cap": 64, "u8_lds": 51200, "u8_sched": 0,
-//             "ms": 1.5, "candidates": 9, "table": [[64, 51200, 0, 81920, 64, 1.5], ...]}
-// (table rows: u8 tile cap, u8 LDS, u8 schedule, f32 LDS, f32 tile cap, ms per run)
+//             "u8_td_rows": 4, "ms": 1.5, "candidates": 9, "table": [[64, 51200, 0, 4, 81920, 64, 1.5], ...]}
+// (table rows: u8 tile cap, u8 LDS, u8 schedule, u8 TD rows per work-group, f32 LDS, f32 tile cap,
+// ms per run)
 #include <algorithm>
 #include <cstdio>
 #include <cstdlib>
@@ -49,6 +50,10 @@ TuneParams default_tune() {
     if (const char* e = std::getenv("RFIM_U8_SCHED")) {
         const int v = std::atoi(e);
         if (v == 0 || v == 1) p.u8_sched = v;
+    }
+    if (const char* e = std::getenv("RFIM_U8_TD_ROWS")) {
+        const int v = std::atoi(e);
+        if (v == 2 || v == 4 || v == 8) p.u8_td_rows = v;
     }
     return p;
 }
@@ -106,14 +111,16 @@ rfim_status tune_cache_lookup(const char* path, const rfim_beam* shapes, int32_t
     const std::string pre = entry_prefix(tune_key(shapes, nbeams, steps, nsteps));
     for (const std::string& l : lines) {
         if (l.compare(0, pre.size(), pre) != 0) continue;
-        double a = 0, b = 0, c = 0, d = 51200, e = 0;
+        double a = 0, b = 0, c = 0, d = 51200, e = 0, f = 4;
         if (!field(l, "u8_tile_cap", &a) || !field(l, "f32_lds", &b) || !field(l, "f32_tile_cap", &c))
             return RFIM_ERR_INVALID_ARG;
-        (void)field(l, "u8_lds", &d);     // optional, default budget
-        (void)field(l, "u8_sched", &e);   // optional, default schedule
+        (void)field(l, "u8_lds", &d);       // optional, default budget
+        (void)field(l, "u8_sched", &e);     // optional, default schedule
+        (void)field(l, "u8_td_rows", &f);   // optional, default rows per work-group
         if (a < 4 || a > 64 || b < 1024 || b > (1 << 20) || c < 4 || c > 64 || d < 4096 || d > (1 << 20) ||
-            (e != 0 && e != 1))
+            (e != 0 && e != 1) || (f != 2 && f != 4 && f != 8))
             return RFIM_ERR_INVALID_ARG;
+        out->u8_td_rows = (int)f;
         out->u8_tile_cap = (int)a;
         out->f32_lds = (size_t)b;
         out->f32_tile_cap = (int)c;
@@ -141,14 +148,14 @@ rfim_status tune_cache_store(const char* path, const rfim_beam* shapes, int32_t 
     char buf[256];
     std::snprintf(buf, sizeof buf,
                   "\"u8_tile_cap\": %d, \"f32_lds\": %zu, \"f32_tile_cap\": %d, \"u8_lds\": %zu, "
-                  "\"u8_sched\": %d, \"ms\": %.6f, \"candidates\": %zu, \"table\": [",
-                  p.u8_tile_cap, p.f32_lds, p.f32_tile_cap, p.u8_lds, p.u8_sched, ms, table.size());
+                  "\"u8_sched\": %d, \"u8_td_rows\": %d, \"ms\": %.6f, \"candidates\": %zu, \"table\": [",
+                  p.u8_tile_cap, p.f32_lds, p.f32_tile_cap, p.u8_lds, p.u8_sched, p.u8_td_rows, ms, table.size());
     std::string e = pre + buf;
-    // table rows: [u8 tile cap, u8 LDS, u8 schedule, f32 LDS, f32 tile cap, ms per run]
+    // table rows: [u8 tile cap, u8 LDS, u8 schedule, u8 TD rows, f32 LDS, f32 tile cap, ms per run]
     for (size_t i = 0; i < table.size(); i++) {
         const TuneRow& r = table[i];
-        std::snprintf(buf, sizeof buf, "%s[%d, %zu, %d, %zu, %d, %.6f]", i ? ", " : "", r.p.u8_tile_cap,
-                      r.p.u8_lds, r.p.u8_sched, r.p.f32_lds, r.p.f32_tile_cap, r.ms);
+        std::snprintf(buf, sizeof buf, "%s[%d, %zu, %d, %d, %zu, %d, %.6f]", i ? ", " : "", r.p.u8_tile_cap,
+                      r.p.u8_lds, r.p.u8_sched, r.p.u8_td_rows, r.p.f32_lds, r.p.f32_tile_cap, r.ms);
         e += buf;
     }
     e += "]}";
@@ -261,6 +268,7 @@ rfim_status rfim_tune_lookup(const char* path, const rfim_beam* shapes, int32_t 
     params[2] = p.f32_tile_cap;
     params[3] = (int64_t)p.u8_lds;
     params[4] = p.u8_sched;
+    params[5] = p.u8_td_rows;
     return RFIM_OK;
 }
 
@@ -273,9 +281,10 @@ rfim_status rfim_tune_store(const char* path, const rfim_beam* shapes, int32_t n
     p.f32_tile_cap = (int)params[2];
     p.u8_lds = (size_t)params[3];
     p.u8_sched = (int)params[4];
+    p.u8_td_rows = (int)params[5];
     if (p.u8_tile_cap < 4 || p.u8_tile_cap > 64 || p.f32_lds < 1024 || p.f32_lds > (1u << 20) ||
         p.f32_tile_cap < 4 || p.f32_tile_cap > 64 || p.u8_lds < 4096 || p.u8_lds > (1u << 20) ||
-        (p.u8_sched != 0 && p.u8_sched != 1))
+        (p.u8_sched != 0 && p.u8_sched != 1) || (p.u8_td_rows != 2 && p.u8_td_rows != 4 && p.u8_td_rows != 8))
         return RFIM_ERR_INVALID_ARG;
     return tune_cache_store(path, shapes, nbeams, steps, nsteps, p, ms, {});
 }
@@ -327,53 +336,38 @@ rfim_status rfim_autotune(const rfim_beam* shapes, int32_t nbeams, const rfim_st
         return v;
     };
 
-    // candidates: the default first (it produces the reference outputs)
-    std::vector<TuneParams> cands;
+    // Search: the default first (it produces the reference outputs), then the
+    // uint8 axes (tile cap, LDS budget, schedule, TD rows per work-group) on
+    // the default float32 setting, then the float32 axes (LDS budget, tile
+    // cap) on the best uint8 setting found.
     const TuneParams def = default_tune();
-    cands.push_back(def);
-    const int u8caps[] = {16, 32, 64};
-    const size_t u8lds[] = {51200, 102400};
-    const int u8sched[] = {0, 1};
-    const size_t f32lds[] = {40960, 81920, 163840};
-    const int f32caps[] = {8, 64};
-    for (int a : u8caps)
-        for (size_t ul : u8lds)
-            for (int sc : u8sched)
-                for (size_t l : f32lds)
-                    for (int c : f32caps) {
-                        if (!any_u8 && (a != def.u8_tile_cap || ul != def.u8_lds || sc != def.u8_sched)) continue;
-                        if (!any_f32 && (l != def.f32_lds || c != def.f32_tile_cap)) continue;
-                        TuneParams p;
-                        p.u8_tile_cap = a;
-                        p.u8_lds = ul;
-                        p.u8_sched = sc;
-                        p.f32_lds = l;
-                        p.f32_tile_cap = c;
-                        if (p.u8_tile_cap == def.u8_tile_cap && p.u8_lds == def.u8_lds &&
-                            p.u8_sched == def.u8_sched && p.f32_lds == def.f32_lds &&
-                            p.f32_tile_cap == def.f32_tile_cap)
-                            continue;
-                        cands.push_back(p);
-                    }
-
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) st = RFIM_ERR_DEVICE;
     double best = 1e30;
     TuneParams bestp = def;
     std::vector<TuneRow> table;
     const int reps = 5;
-    for (size_t ci = 0; ci < cands.size() && st == RFIM_OK; ci++) {
+    size_t ci = 0;
+    auto same = [](const TuneParams& x, const TuneParams& y) {
+        return x.u8_tile_cap == y.u8_tile_cap && x.u8_lds == y.u8_lds && x.u8_sched == y.u8_sched &&
+               x.u8_td_rows == y.u8_td_rows && x.f32_lds == y.f32_lds && x.f32_tile_cap == y.f32_tile_cap;
+    };
+    auto evaluate = [&](const TuneParams& cand) {
+        if (st != RFIM_OK) return;
+        if (ci > 0 && same(cand, def)) return;   // the default was timed first
+        const bool ref = ci == 0;
+        ci++;
         rfim_plan* plan = nullptr;
-        const rfim_status pc = plan_create_tuned(shapes, nbeams, steps, nsteps, cands[ci], &plan);
+        const rfim_status pc = plan_create_tuned(shapes, nbeams, steps, nsteps, cand, &plan);
         if (pc != RFIM_OK) {
             // a candidate whose tiles do not fit this device is not applicable;
             // the default must always be
-            if (ci == 0 || pc != RFIM_ERR_UNSUPPORTED) st = pc;
-            continue;
+            if (ref || pc != RFIM_ERR_UNSUPPORTED) st = pc;
+            return;
         }
-        const std::vector<rfim_beam> bv = beams_to(ci == 0);
-        st = rfim_pipeline_run(bv.data(), nbeams, steps, nsteps, plan, stream);   // warm-up (the reference for ci 0)
-        if (st == RFIM_OK && ci > 0) {
+        const std::vector<rfim_beam> bv = beams_to(ref);
+        st = rfim_pipeline_run(bv.data(), nbeams, steps, nsteps, plan, stream);   // warm-up (the reference first)
+        if (st == RFIM_OK && !ref) {
             // bit-identical to the default configuration over [0, nsamp) of every row
             if (hipMemsetAsync(d_diff, 0, sizeof(unsigned long long), s) != hipSuccess) st = RFIM_ERR_DEVICE;
             for (int i = 0; i < nbeams && st == RFIM_OK; i++) {
@@ -393,10 +387,10 @@ rfim_status rfim_autotune(const rfim_beam* shapes, int32_t nbeams, const rfim_st
                 st = RFIM_ERR_DEVICE;
             if (st == RFIM_OK && diff != 0) {
                 std::fprintf(stderr,
-                             "rfim_autotune: candidate %zu (u8 tile cap %d, u8 LDS %zu, u8 schedule %d, f32 LDS %zu, "
-                             "f32 tile cap %d) differs from the default configuration in %llu bytes\n",
-                             ci, cands[ci].u8_tile_cap, cands[ci].u8_lds, cands[ci].u8_sched, cands[ci].f32_lds,
-                             cands[ci].f32_tile_cap, diff);
+                             "rfim_autotune: candidate (u8 tile cap %d, u8 LDS %zu, u8 schedule %d, u8 TD rows %d, "
+                             "f32 LDS %zu, f32 tile cap %d) differs from the default configuration in %llu bytes\n",
+                             cand.u8_tile_cap, cand.u8_lds, cand.u8_sched, cand.u8_td_rows, cand.f32_lds,
+                             cand.f32_tile_cap, diff);
                 st = RFIM_ERR_MISMATCH;
             }
         }
@@ -410,14 +404,38 @@ rfim_status rfim_autotune(const rfim_beam* shapes, int32_t nbeams, const rfim_st
                 st = RFIM_ERR_DEVICE;
             if (st == RFIM_OK) {
                 const double per = ms / reps;
-                table.push_back({cands[ci], per});
+                table.push_back({cand, per});
                 if (per < best) {
                     best = per;
-                    bestp = cands[ci];
+                    bestp = cand;
                 }
             }
         }
         (void)rfim_plan_destroy(plan);
+    };
+    evaluate(def);
+    if (any_u8) {
+        for (int a : {16, 32, 64})
+            for (size_t ul : {(size_t)51200, (size_t)102400})
+                for (int sc : {0, 1})
+                    for (int rows : {2, 4, 8}) {
+                        TuneParams p = def;
+                        p.u8_tile_cap = a;
+                        p.u8_lds = ul;
+                        p.u8_sched = sc;
+                        p.u8_td_rows = rows;
+                        evaluate(p);
+                    }
+    }
+    if (any_f32) {
+        const TuneParams base = bestp;
+        for (size_t l : {(size_t)40960, (size_t)81920, (size_t)163840})
+            for (int c : {8, 64}) {
+                TuneParams p = base;
+                p.f32_lds = l;
+                p.f32_tile_cap = c;
+                if (!same(p, base)) evaluate(p);
+            }
     }
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);

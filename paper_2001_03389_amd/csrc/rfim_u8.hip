@@ -249,19 +249,23 @@ __device__ bool td_decide(const Segment& seg, uint64_t n, uint32_t hv[4], uint64
 }
 
 // LDS of one TD row group (one row per wave)
-struct TdShared {
-    uint32_t hist[kRowsPerWG][kHistCopies * kHistPitch];
-    int lo[kRowsPerWG][kMaxSteps], hi[kRowsPerWG][kMaxSteps], r[kRowsPerWG][kMaxSteps];
-    unsigned long long mv[kRowsPerWG][kMaxSteps];
-    int beam[kRowsPerWG];
+template <int R>
+struct TdSharedR {
+    uint32_t hist[R][kHistCopies * kHistPitch];
+    int lo[R][kMaxSteps], hi[R][kMaxSteps], r[R][kMaxSteps];
+    unsigned long long mv[R][kMaxSteps];
+    int beam[R];
 };
+using TdShared = TdSharedR<kRowsPerWG>;
 
-// Rows g0 .. g0 + kRowsPerWG - 1 of a launch's row space, wave w on row
+// Rows g0 .. g0 + R - 1 of a launch's row space (R waves), wave w on row
 // g0 + w; rows at or past `row_end` are skipped.  Called by every thread of
 // the work-group.
+template <int R>
 __device__ __attribute__((always_inline)) inline void td_row_group(const DevBeam* __restrict__ beams, int nbeams, int64_t g0, int64_t row_end,
                                     const Segment& seg, uint32_t* __restrict__ rec,
-                                    unsigned long long* __restrict__ counts, int count_stride, TdShared& sh) {
+                                    unsigned long long* __restrict__ counts, int count_stride,
+                                    TdSharedR<R>& sh) {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int64_t g = g0 + wave;
     // waves past the last row skip the row work but still reach the
@@ -354,7 +358,7 @@ __device__ __attribute__((always_inline)) inline void td_row_group(const DevBeam
         __syncthreads();
         const int j = threadIdx.x;
         if (j < seg.n_td) {
-            const int nw = (int)min((int64_t)kRowsPerWG, row_end - g0);
+            const int nw = (int)min((int64_t)R, row_end - g0);
             int cb = sh.beam[0];
             unsigned long long sum = 0;
             for (int w = 0; w < nw; w++) {
@@ -371,13 +375,15 @@ __device__ __attribute__((always_inline)) inline void td_row_group(const DevBeam
 }
 
 
-__global__ __launch_bounds__(kBlock) void k_td_rows_u8(const DevBeam* __restrict__ beams,
+// R rows (waves) per work-group, a tuning parameter
+template <int R>
+__global__ __launch_bounds__(64 * R) void k_td_rows_u8(const DevBeam* __restrict__ beams,
                                                        int nbeams, int64_t total_rows, Segment seg,
                                                        uint32_t* __restrict__ rec,
                                                        unsigned long long* __restrict__ counts,
                                                        int count_stride) {
-    __shared__ TdShared sh;
-    td_row_group(beams, nbeams, (int64_t)blockIdx.x * kRowsPerWG, total_rows, seg, rec, counts, count_stride, sh);
+    __shared__ TdSharedR<R> sh;
+    td_row_group<R>(beams, nbeams, (int64_t)blockIdx.x * R, total_rows, seg, rec, counts, count_stride, sh);
 }
 
 namespace {
@@ -1379,8 +1385,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
         const int64_t local = it - bm.item0;
         const int64_t ntd = seg.n_td > 0 ? (bm.C + kRowsPerWG - 1) / kRowsPerWG : 0;
         if (local < ntd) {
-            td_row_group(beams, nbeams, bm.row0 + local * kRowsPerWG, bm.row0 + bm.C, seg, rec, counts,
-                         count_stride, tsh);
+            td_row_group<kRowsPerWG>(beams, nbeams, bm.row0 + local * kRowsPerWG, bm.row0 + bm.C, seg, rec, counts,
+                                     count_stride, tsh);
             __syncthreads();   // every wave's records are written (work-group scope)
             if (threadIdx.x == 0) __hip_atomic_fetch_add(&done[lo], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
             continue;
@@ -1437,13 +1443,20 @@ hipError_t launch_persist_u8(const DevBeam* d_beams, int nbeams, const PersistQu
     return hipGetLastError();
 }
 
-hipError_t launch_td_rows_u8(const DevBeam* d_beams, int nbeams, int64_t total_rows,
+hipError_t launch_td_rows_u8(const DevBeam* d_beams, int nbeams, int64_t total_rows, int rows_per_wg,
                              const Segment& seg, uint32_t* d_rec, unsigned long long* d_counts,
                              int count_stride, hipStream_t s) {
     if (total_rows <= 0) return hipSuccess;
-    const int64_t wgs = (total_rows + kRowsPerWG - 1) / kRowsPerWG;
-    hipLaunchKernelGGL(k_td_rows_u8, dim3((unsigned)wgs), dim3(kBlock), 0, s, d_beams, nbeams,
-                       total_rows, seg, d_rec, d_counts, count_stride);
+    auto go = [&](auto kern, int R) {
+        const int64_t wgs = (total_rows + R - 1) / R;
+        hipLaunchKernelGGL(kern, dim3((unsigned)wgs), dim3(64 * R), 0, s, d_beams, nbeams, total_rows, seg, d_rec,
+                           d_counts, count_stride);
+    };
+    switch (rows_per_wg) {
+        case 2: go(k_td_rows_u8<2>, 2); break;
+        case 8: go(k_td_rows_u8<8>, 8); break;
+        default: go(k_td_rows_u8<4>, 4); break;
+    }
     return hipGetLastError();
 }
 

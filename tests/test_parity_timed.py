@@ -304,3 +304,52 @@ def test_stress_full_pipeline_sampled(rf, stress_beam, inplace):
         assert counts[j] >= int(((wf >> j) & 1).sum())
     del xi, o
     torch.cuda.empty_cache()
+
+
+# ------------------------------------- TD rows per work-group (tuning axis)
+@pytest.mark.parametrize("rows", [2, 8])
+def test_td_rows_per_group_full_size(rf, uneven_u8, tmp_path, rows):
+    """The uint8 TD pass with 2 or 8 rows per work-group, forced through the
+    tuning cache, on full-size beams of two uneven shapes (flags on and off)."""
+    beams, ref = uneven_u8
+    steps = list(synth.STEPS_ARTS1)
+    for shape in ("1536x12500", "768x16384"):
+        for flags in (False, True):
+            x = beams[shape]
+            cache = str(tmp_path / f"tune_{shape}_{flags}.json")
+            shp = [rf.shape_beam("u8", x.shape[0], x.shape[1], flags=flags)]
+            rf.tune_store(cache, shp, steps, (64, 81920, 64, 51200, 0, rows))
+            assert rf.tune_lookup(cache, shp, steps)[5] == rows
+            say(f"td rows {rows} {shape} flags={flags}")
+            _, out, fl, counts = run_one(rf, x, steps, flags, tune_cache=cache)
+            want, wf = ref[shape]
+            np.testing.assert_array_equal(out, want)
+            if flags:
+                np.testing.assert_array_equal(fl, wf)
+            assert counts == oracle_counts(wf, len(steps))
+
+
+@pytest.mark.parametrize("rows", [2, 4, 8])
+def test_td_rows_groups_spanning_beams(rf, tmp_path, rows):
+    """Work-groups of 2, 4 or 8 rows over beams whose channel counts are not
+    multiples of the group (groups spanning beams, short last group): TD-only
+    lists, outputs and per-beam counts against the oracle."""
+    import torch
+    steps = [synth.td(3.0), synth.td(2.5, "median"), synth.td(2.75)]
+    shapes = [(5, 3001), (63, 2000), (130, 777), (1, 4096), (250, 1500), (7, 9000)]
+    xs = [synth.make_beam(synth.BeamSpec("u8", C, T, 7, i)) for i, (C, T) in enumerate(shapes)]
+    ref = oracle_pool.pipelines([(x, steps, True, None) for x in xs])
+    cache = str(tmp_path / "tune.json")
+    shp = [rf.shape_beam("u8", C, T) for C, T in shapes]
+    rf.tune_store(cache, shp, steps, (64, 81920, 64, 51200, 0, rows))
+    ins = [torch.from_numpy(x).cuda() for x in xs]
+    outs = [torch.full_like(x, 0x5A) for x in ins]
+    plan = rf.Plan(ins, steps, outputs=outs, tune_cache=cache)
+    say(f"td rows {rows}: six beams")
+    rf.rfim_pipeline_run(ins, steps, outputs=outs, plan=plan)
+    torch.cuda.synchronize()
+    counts = plan.flag_counts()
+    plan.close()
+    for i, (want, wf) in enumerate(ref):
+        np.testing.assert_array_equal(outs[i].cpu().numpy(), want, err_msg=f"beam {i}")
+        assert counts[i] == oracle_counts(wf, len(steps)), i

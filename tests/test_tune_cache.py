@@ -29,24 +29,24 @@ def test_round_trip_replace_and_json(tmp_path):
     rf.tune_store(p, shapes_a(), STEPS, (32, 81920, 64), 1.25)
     other = [rf.shape_beam("u8", 384, 25000, flags=True)]
     rf.tune_store(p, other, STEPS, (16, 40960, 8), 0.5)
-    assert rf.tune_lookup(p, shapes_a(), STEPS) == (32, 81920, 64, 51200, 0)
-    assert rf.tune_lookup(p, other, STEPS) == (16, 40960, 8, 51200, 0)
-    rf.tune_store(p, shapes_a(), STEPS, (64, 163840, 8, 102400, 1), 1.0)    # replaces
-    assert rf.tune_lookup(p, shapes_a(), STEPS) == (64, 163840, 8, 102400, 1)
+    assert rf.tune_lookup(p, shapes_a(), STEPS) == (32, 81920, 64, 51200, 0, 4)
+    assert rf.tune_lookup(p, other, STEPS) == (16, 40960, 8, 51200, 0, 4)
+    rf.tune_store(p, shapes_a(), STEPS, (64, 163840, 8, 102400, 1, 8), 1.0)    # replaces
+    assert rf.tune_lookup(p, shapes_a(), STEPS) == (64, 163840, 8, 102400, 1, 8)
     doc = json.load(open(p))
     assert len(doc) == 2
-    assert all(set(v) >= {"u8_tile_cap", "f32_lds", "f32_tile_cap", "u8_lds", "u8_sched", "ms"}
+    assert all(set(v) >= {"u8_tile_cap", "f32_lds", "f32_tile_cap", "u8_lds", "u8_sched", "u8_td_rows", "ms"}
                for v in doc.values())
 
 
 def test_entry_without_schedule_reads_as_default(tmp_path):
-    """Cache entries written before the schedule parameter existed read as
-    the two-pass schedule."""
+    """Cache entries written before the schedule and TD-rows parameters
+    existed read as the two-pass schedule with four rows per work-group."""
     p = str(tmp_path / "tune.json")
-    rf.tune_store(p, shapes_a(), STEPS, (32, 81920, 64, 51200, 1), 1.0)
-    txt = open(p).read().replace('"u8_sched": 1, ', "")
+    rf.tune_store(p, shapes_a(), STEPS, (32, 81920, 64, 51200, 1, 2), 1.0)
+    txt = open(p).read().replace('"u8_sched": 1, ', "").replace('"u8_td_rows": 2, ', "")
     open(p, "w").write(txt)
-    assert rf.tune_lookup(p, shapes_a(), STEPS) == (32, 81920, 64, 51200, 0)
+    assert rf.tune_lookup(p, shapes_a(), STEPS) == (32, 81920, 64, 51200, 0, 4)
 
 
 @pytest.mark.parametrize("variant", ["flags", "stride", "k-ulp", "replace", "bin", "order"])
@@ -81,6 +81,7 @@ def test_malformed_entry_rejected(tmp_path):
 
 def test_store_rejects_out_of_range(tmp_path):
     p = str(tmp_path / "tune.json")
-    for bad in [(2, 81920, 64), (32, 10, 64), (32, 81920, 128), (32, 81920, 64, 100), (32, 81920, 64, 51200, 2)]:
+    for bad in [(2, 81920, 64), (32, 10, 64), (32, 81920, 128), (32, 81920, 64, 100), (32, 81920, 64, 51200, 2),
+                (32, 81920, 64, 51200, 0, 3)]:
         with pytest.raises(rf.RfimError):
             rf.tune_store(p, shapes_a(), STEPS, bad, 1.0)
