@@ -531,6 +531,14 @@ __device__ inline int fd_column_f32(float (&x)[BPL][B], uint32_t (&fw)[BPL][B / 
     const double sc = ldexp(1.0, 174 - EM), sc2 = ldexp(1.0, 198 - EM);
     const int e = TWO ? EM - 198 : EM - 174;
     lc[0] = lc[1] = lc[2] = lc[3] = 0;
+    // Bin medians, kept across median steps: replacing a bin's cut samples by
+    // its lower median leaves that value the lower median (the counts on
+    // either side only shrink), so once taken it stays valid until a mean step
+    // changes the bin.  When any lane of the wave first needs one, every lane
+    // takes all of its bins' medians at once (the sorting network runs once
+    // per wave instead of once per step).
+    float medc[BPL];
+    bool medv = false;   // wave-uniform
     for (int s = 0; s < seg.n_fd; s++) {
         const SegStep& st = seg.fd[s];
         i128 S[BPL];
@@ -613,16 +621,31 @@ __device__ inline int fd_column_f32(float (&x)[BPL][B], uint32_t (&fw)[BPL][B / 
                 Los[kk] = f32_round_ratio(S[kk] - (i128)z, B, e, kRU);
             }
         }
+        uint64_t fms[BPL];
+        bool anyf = false;
+#pragma unroll
+        for (int kk = 0; kk < BPL; kk++) {
+            uint64_t fm = 0;
+            const float H = Hs[kk], Lo = Los[kk];
+#pragma unroll
+            for (int j = 0; j < B; j++) fm |= (uint64_t)(x[kk][j] < Lo || x[kk][j] > H) << j;
+            fms[kk] = act[kk] ? fm : 0;
+            anyf |= fms[kk] != 0;
+        }
+        const bool wave_cut = __ballot(anyf) != 0;
+        if (st.replace == RFIM_REPLACE_MEDIAN && wave_cut && !medv) {
+#pragma unroll
+            for (int kk = 0; kk < BPL; kk++) medc[kk] = bin_median<B>(x[kk]);
+            medv = true;
+        }
+        if (st.replace != RFIM_REPLACE_MEDIAN && wave_cut) medv = false;
 #pragma unroll
         for (int kk = 0; kk < BPL; kk++) {
             if (!act[kk]) continue;
-            const float H = Hs[kk], Lo = Los[kk];
-            uint64_t fm = 0;
-#pragma unroll
-            for (int j = 0; j < B; j++) fm |= (uint64_t)(x[kk][j] < Lo || x[kk][j] > H) << j;
+            const uint64_t fm = fms[kk];
             if (!fm) continue;
             float r;
-            if (st.replace == RFIM_REPLACE_MEDIAN) r = bin_median<B>(x[kk]);
+            if (st.replace == RFIM_REPLACE_MEDIAN) r = medc[kk];
             else if (TWO || !f32_mean_fast((double)(int64_t)S[kk], (double)B, e, &r))
                 r = f32_round_ratio(S[kk], B, e, kRN);
             if (below_window(__float_as_uint(r), thr2)) bad |= 1u;
@@ -802,7 +825,10 @@ __global__ __launch_bounds__(kF32Block) void k_fused_f32(const DevBeam* __restri
     // capacity, and when the tile goes straight out, mapped in place.  kB1
     // items per thread have their row loads and interval loads in flight
     // together.
-    constexpr int kB1 = 4;
+    // 16 items (a 4096-channel tile's whole share of a thread) keep about
+    // 64 KB of loads in flight per CU-resident work-group pair; four left the
+    // phase waiting on memory latency.
+    constexpr int kB1 = 16;
     for (int it0 = tid; it0 < nitems; it0 += kB1 * kF32Block) {
         float xs[kB1][4];
         float2 fr[kB1];
@@ -934,7 +960,9 @@ __global__ __launch_bounds__(kF32Block) void k_fused_f32(const DevBeam* __restri
     }
     __syncthreads();
 
-    // ---- phase 3: tile back to rows
+    // ---- phase 3: tile back to rows (four items per thread per pass: their
+    // LDS reads are issued together)
+#pragma unroll 4
     for (int it = tid; it < nitems; it += kF32Block) {
         const int c = it >> tq_log;
         const int q = it & (TQ - 1);
