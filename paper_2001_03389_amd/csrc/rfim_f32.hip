@@ -358,10 +358,18 @@ __device__ inline void td_row_f32(const DevBeam& bm, int64_t c, const Segment& s
                 // units of the second window: S = S0 * 2^24 + S1, Q = Q0 * 2^48 + Q1
                 const i128 Sc = St * ((i128)1 << 24) + St1;
                 const U512 D = d_combine(n, q_combine(Qt, Qt1), Sc);
-                const u128 z = zmax_k2w(1, D, st.kx, kZcap2);
-                H = f32_round_ratio(Sc + (i128)z, n, e2, kRD);
-                Lo = f32_round_ratio(Sc - (i128)z, n, e2, kRU);
-                rm = f32_round_ratio(Sc, n, e2, kRN);
+                bool cert = false;   // certified FP64 evaluation, else exact
+                if (st.kx.mode == 0) {
+                    const double Sd = i128_to_double(Sc);
+                    const double zr = st.kx.k * sqrt(u512_to_double(D));
+                    cert = f32_cut_fast(Sd, zr, (double)n, e2, &H, &Lo) && f32_mean_fast(Sd, (double)n, e2, &rm);
+                }
+                if (!cert) {
+                    const u128 z = zmax_k2w(1, D, st.kx, kZcap2);
+                    H = f32_round_ratio(Sc + (i128)z, n, e2, kRD);
+                    Lo = f32_round_ratio(Sc - (i128)z, n, e2, kRU);
+                    rm = f32_round_ratio(Sc, n, e2, kRN);
+                }
             }
             const float r = st.replace == RFIM_REPLACE_MEDIAN ? med : rm;
             if (lane == 0) {
@@ -543,6 +551,7 @@ __device__ inline int fd_column_f32(float (&x)[BPL][B], uint32_t (&fw)[BPL][B / 
         const SegStep& st = seg.fd[s];
         i128 S[BPL];
         u128 z = 0, Rv = 0;
+        U512 Vw = u512_from(0);   // two windows: the sum of Z^2 (in second-window units)
         double zr = 0.0;
         if (!TWO) {
             u128 V = 0;
@@ -596,7 +605,8 @@ __device__ inline int fd_column_f32(float (&x)[BPL][B], uint32_t (&fw)[BPL][B / 
                 if (act[kk]) V = u512_add(V, d_combine(B, q_combine(Q0, Q1), S[kk]));
             }
             V = group_add_u256(V, G2);
-            z = zmax_k2w(C, u512_mul_u128(V, (u128)B), st.kx, kZcap2);
+            Vw = u512_mul_u128(V, (u128)B);
+            zr = st.kx.mode == 0 ? st.kx.k * sqrt(u512_to_double(Vw) / (double)C) : 0.0;
         }
         const int bit = st.bit;
         uint32_t bad = 0;
@@ -608,12 +618,13 @@ __device__ inline int fd_column_f32(float (&x)[BPL][B], uint32_t (&fw)[BPL][B / 
         for (int kk = 0; kk < BPL; kk++) {
             cert[kk] = false;
             Hs[kk] = Los[kk] = 0.0f;
-            if (!TWO && st.kx.mode == 0 && act[kk])
-                cert[kk] = f32_cut_fast((double)(int64_t)S[kk], zr, (double)B, e, &Hs[kk], &Los[kk]);
+            if (st.kx.mode == 0 && act[kk])
+                cert[kk] = f32_cut_fast(TWO ? i128_to_double(S[kk]) : (double)(int64_t)S[kk], zr, (double)B, e,
+                                        &Hs[kk], &Los[kk]);
             need |= act[kk] && !cert[kk];
         }
         if (need) {
-            if (!TWO) z = zmax_k2(C, Rv, st.kx, kZcap);
+            z = TWO ? zmax_k2w(C, Vw, st.kx, kZcap2) : zmax_k2(C, Rv, st.kx, kZcap);
 #pragma unroll
             for (int kk = 0; kk < BPL; kk++) {
                 if (!act[kk] || cert[kk]) continue;
@@ -646,7 +657,7 @@ __device__ inline int fd_column_f32(float (&x)[BPL][B], uint32_t (&fw)[BPL][B / 
             if (!fm) continue;
             float r;
             if (st.replace == RFIM_REPLACE_MEDIAN) r = medc[kk];
-            else if (TWO || !f32_mean_fast((double)(int64_t)S[kk], (double)B, e, &r))
+            else if (!f32_mean_fast(TWO ? i128_to_double(S[kk]) : (double)(int64_t)S[kk], (double)B, e, &r))
                 r = f32_round_ratio(S[kk], B, e, kRN);
             if (below_window(__float_as_uint(r), thr2)) bad |= 1u;
             else if (!TWO && below_window(__float_as_uint(r), thr)) bad |= 2u;
