@@ -142,6 +142,94 @@ __device__ inline uint32_t wg_select_key(uint64_t rank, uint32_t* s_hist, uint32
     return prefix;
 }
 
+// Key of rank `rank` among the values the callback visits, by value bins: a
+// value x in [lo, hi) (by IEEE totalOrder) goes to bin (x - lo) * NB / (hi - lo)
+// rounded down, a map that never decreases as x grows, so the bins keep the
+// values' order; a prefix sum over the bins finds the one that holds the rank,
+// and that bin's values, at most CAP of them, are ranked exactly by key.
+// Returns false, the same on every thread, when the rank lies outside the
+// range or its bin holds more than CAP values (the caller then runs
+// wg_select_key).  The caller zeroes s_bins[0, NB) and s_m[0, 8) and
+// synchronises first.  All NT threads call.
+template <int NT, int NB, int CAP, typename Visit>
+__device__ inline bool wg_select_bins(uint32_t rank, float lo, float hi, uint32_t* s_bins, uint32_t* s_cand,
+                                      uint32_t* s_tot, uint32_t* s_m, Visit&& visit, uint32_t* key) {
+    constexpr int NW = NT / 64;
+    constexpr int BPT = NB / NT;
+    static_assert(BPT * NT == NB, "bins per thread");
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const uint32_t klo = f32_key(__float_as_uint(lo)), khi = f32_key(__float_as_uint(hi));
+    const float inv = (float)NB / (hi - lo);   // finite and positive (the caller checks)
+    auto bin_of = [&](float x) {
+        const int b = (int)((x - lo) * inv);
+        return b < NB ? b : NB - 1;
+    };
+    uint32_t below = 0;
+    visit([&](float x) {
+        const uint32_t k = f32_key(__float_as_uint(x));
+        if (k < klo) below++;
+        else if (k < khi) atomicAdd(&s_bins[bin_of(x)], 1u);
+    });
+    below = wave_add_u32(below);
+    if (lane == 0 && below) atomicAdd(&s_m[0], below);
+    __syncthreads();
+    below = s_m[0];
+    uint32_t c[BPT], sum = 0;
+#pragma unroll
+    for (int j = 0; j < BPT; j++) {
+        c[j] = s_bins[tid * BPT + j];
+        sum += c[j];
+    }
+    uint32_t incl = sum;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t t = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += t;
+    }
+    if (lane == 63) s_tot[wave] = incl;
+    __syncthreads();
+    if (rank >= below) {
+        const uint32_t r2 = rank - below;
+        uint32_t acc = incl - sum;
+        for (int w = 0; w < wave; w++) acc += s_tot[w];
+        if (acc <= r2 && r2 < acc + sum) {
+#pragma unroll
+            for (int j = 0; j < BPT; j++) {
+                if (r2 < acc + c[j]) {
+                    s_m[1] = (uint32_t)(tid * BPT + j);
+                    s_m[2] = r2 - acc;   // rank inside the bin
+                    s_m[3] = c[j];
+                    s_m[5] = 1;
+                    break;
+                }
+                acc += c[j];
+            }
+        }
+    }
+    __syncthreads();
+    const uint32_t m = s_m[3];
+    if (!s_m[5] || m > (uint32_t)CAP) return false;
+    const int jb = (int)s_m[1];
+    visit([&](float x) {
+        const uint32_t k = f32_key(__float_as_uint(x));
+        if (k >= klo && k < khi && bin_of(x) == jb) s_cand[atomicAdd(&s_m[4], 1u)] = k;
+    });
+    __syncthreads();
+    const uint32_t rr = s_m[2];
+    for (uint32_t i = tid; i < m; i += NT) {
+        const uint32_t my = s_cand[i];
+        uint32_t pos = 0;
+        for (uint32_t q = 0; q < m; q++) {
+            const uint32_t o = s_cand[q];
+            pos += (o < my || (o == my && q < i)) ? 1u : 0u;
+        }
+        if (pos == rr) s_m[6] = my;
+    }
+    __syncthreads();
+    *key = s_m[6];
+    return true;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -162,7 +250,8 @@ __device__ inline void td_row_f32(const DevBeam& bm, int64_t c, const Segment& s
     constexpr int VR = VPT - VL;
     __shared__ uint32_t s_hist[NW * 256];
     __shared__ float s_row[VL > 0 ? VL * NT : 1];
-    __shared__ uint32_t s_tot[NW], s_sel[2];
+    __shared__ uint32_t s_tot[NW], s_sel[2], s_msel[8];
+    __shared__ double s_mom[NW][2];
     __shared__ int64_t s_S[NW], s_S1[NW];
     __shared__ uint64_t s_Q[NW][2], s_Q1[NW][2];
     __shared__ uint32_t s_u[NW][2];
@@ -187,8 +276,22 @@ __device__ inline void td_row_f32(const DevBeam& bm, int64_t c, const Segment& s
         if (i < VR) v[i < VR ? i : 0] = x;
         else s_row[(i - VR) * NT + tid] = x;
     };
+    // A full row (no padding) takes loops without per-value validity tests:
+    // the compiler keeps those tests as one lane mask per value, more than the
+    // scalar registers hold.
+    const bool full = T == (int64_t)NT * VPT;
     int nv = 0;
-    if (vec) {
+    if (vec && full) {
+#pragma unroll
+        for (int i4 = 0; i4 < VPT / 4; i4++) {
+            const float4 q = *(const float4*)(row + ((int64_t)i4 * NT + tid) * 4);
+            set(4 * i4, q.x);
+            set(4 * i4 + 1, q.y);
+            set(4 * i4 + 2, q.z);
+            set(4 * i4 + 3, q.w);
+        }
+        nv = VPT;
+    } else if (vec) {
 #pragma unroll
         for (int i4 = 0; i4 < VPT / 4; i4++) {
             const int64_t i0 = ((int64_t)i4 * NT + tid) * 4;
@@ -311,11 +414,62 @@ __device__ inline void td_row_f32(const DevBeam& bm, int64_t c, const Segment& s
         __syncthreads();
         float med = cur_med;
         if (st.replace == RFIM_REPLACE_MEDIAN && !known_med) {
-            const uint32_t key = wg_select_key<NT>((uint64_t)(n - 1) / 2, s_hist, s_tot, s_sel, [&](auto&& add) {
+            // The lower median lies within one (population) standard deviation
+            // of the mean, so value bins over mean -+ 1.0625 sd hold it; the
+            // radix select is the fallback for rows the bins do not settle.
+            constexpr int NB = NW * 128, CAP = NW * 128;   // both halves of s_hist
+            double sx = 0.0, sxx = 0.0;   // padding is +0 until the row is written
 #pragma unroll
-                for (int i = 0; i < VPT; i++)
-                    if (i < nv) add(f32_key(__float_as_uint(get(i))));
-            });
+            for (int i = 0; i < VPT; i++) {
+                const double x = (double)get(i);
+                sx += x;
+                sxx += x * x;
+            }
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                sx += __shfl_xor(sx, o, 64);
+                sxx += __shfl_xor(sxx, o, 64);
+            }
+            if (lane == 0) {
+                s_mom[wave][0] = sx;
+                s_mom[wave][1] = sxx;
+            }
+            for (int i = tid; i < NB; i += NT) s_hist[i] = 0;
+            if (tid < 8) s_msel[tid] = 0;
+            __syncthreads();
+            sx = sxx = 0.0;
+            for (int w = 0; w < NW; w++) {
+                sx += s_mom[w][0];
+                sxx += s_mom[w][1];
+            }
+            const double mu = sx / n, sd = sqrt(fmax(sxx / n - mu * mu, 0.0));
+            const double rad = 1.0625 * sd + fabs(mu) * 0x1p-20;
+            const float lo = (float)(mu - rad), hi = (float)(mu + rad);
+            const float wdt = hi - lo;
+            uint32_t key = 0;
+            const bool ok = isfinite(lo) && isfinite(hi) && wdt >= 0x1p-100f && isfinite((float)NB / wdt) &&
+                            wg_select_bins<NT, NB, CAP>((n - 1) / 2, lo, hi, s_hist, s_hist + NB, s_tot, s_msel,
+                                                        [&](auto&& add) {
+                                                            if (full) {
+#pragma unroll
+                                                                for (int i = 0; i < VPT; i++) add(get(i));
+                                                            } else {
+#pragma unroll
+                                                                for (int i = 0; i < VPT; i++)
+                                                                    if (i < nv) add(get(i));
+                                                            }
+                                                        }, &key);
+            if (!ok)
+                key = wg_select_key<NT>((uint64_t)(n - 1) / 2, s_hist, s_tot, s_sel, [&](auto&& add) {
+                    if (full) {
+#pragma unroll
+                        for (int i = 0; i < VPT; i++) add(f32_key(__float_as_uint(get(i))));
+                    } else {
+#pragma unroll
+                        for (int i = 0; i < VPT; i++)
+                            if (i < nv) add(f32_key(__float_as_uint(get(i))));
+                    }
+                });
             med = __uint_as_float(key_f32(key));
         }
         if (wave == 0) {
@@ -393,21 +547,26 @@ __device__ inline void td_row_f32(const DevBeam& bm, int64_t c, const Segment& s
         const int64_t ra = (int64_t)((double)r * sc);   // r lies in the first window (else the row left it)
         dS = 0;
         dQ = 0;
-#pragma unroll
-        for (int i = 0; i < VPT; i++) {
-            if (i < nv) {
-                const float x = get(i);
-                const bool f = x < Lo || x > H;
-                if (f) {
-                    set(i, r);
-                    if (!tiny) {
-                        const int64_t a = (int64_t)((double)x * sc);
-                        dS += ra - a;
-                        dQ += (u128)((i128)ra * ra) - (u128)((i128)a * a);
-                    }
+        auto apply_one = [&](int i) {
+            const float x = get(i);
+            const bool f = x < Lo || x > H;
+            if (f) {
+                set(i, r);
+                if (!tiny) {
+                    const int64_t a = (int64_t)((double)x * sc);
+                    dS += ra - a;
+                    dQ += (u128)((i128)ra * ra) - (u128)((i128)a * a);
                 }
-                cnt += f ? 1u : 0u;
             }
+            cnt += f ? 1u : 0u;
+        };
+        if (full) {
+#pragma unroll
+            for (int i = 0; i < VPT; i++) apply_one(i);
+        } else {
+#pragma unroll
+            for (int i = 0; i < VPT; i++)
+                if (i < nv) apply_one(i);
         }
         cnt = wave_add_u32(cnt);
         if (lane == 0 && cnt) atomicAdd(&s_cnt[j], cnt);

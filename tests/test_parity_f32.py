@@ -187,6 +187,34 @@ def test_edge_cases_f32(rf, case):
     check_against_oracle([x], steps, out, fl)
 
 
+def median_rows(T, rng):
+    """Rows whose lower medians the value-bin select settles, or hands to the
+    radix select: Gaussian, skewed, bimodal (the median between the modes),
+    integers with ties far beyond a bin's capacity at the median, a majority
+    of signed zeros, one huge spike, bandpass-like integer levels."""
+    rows = [rng.standard_normal(T),
+            rng.exponential(1.0, T),
+            np.where(rng.random(T) < 0.5, -5.0, 5.0) + rng.standard_normal(T) * 0.1,
+            rng.integers(0, 4, T).astype(np.float64),
+            np.where(rng.random(T) < 0.5, -0.0, 0.0) + (rng.random(T) < 0.2) * rng.standard_normal(T),
+            np.r_[rng.standard_normal(T - 1), 3.0e37],
+            np.clip(np.round(rng.normal(80, 8, T)), 0, 255),
+            rng.standard_normal(T) * 1e-3 + 7.0]
+    return np.stack(rows).astype(np.float32)
+
+
+@pytest.mark.parametrize("T", [65536, 4099])
+def test_td_median_rows_f32(rf, T):
+    """Row medians at the stress row length and a ragged one, for median
+    steps first and after a mean step: every output bit against the oracle."""
+    x = median_rows(T, np.random.default_rng(T))
+    for steps in ([synth.td(3.0, "median"), synth.td(2.5, "median"), synth.td(2.0, "median")],
+                  [synth.td(3.0), synth.td(2.0, "median"), synth.td(1.5, "median")]):
+        say(f"median rows T={T} steps={steps}")
+        out, fl, _ = gpu_run(rf, [x], steps)
+        check_against_oracle([x], steps, out, fl)
+
+
 @pytest.mark.parametrize("shape", synth.UNEVEN_SHAPES, ids=[f"{c}x{t}" for c, t in synth.UNEVEN_SHAPES])
 def test_uneven_shapes_f32_full(rf, shape):
     """The float32 beams of the batched uneven workload at full size, TD 3.25 +
