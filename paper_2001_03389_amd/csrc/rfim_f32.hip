@@ -418,47 +418,70 @@ __device__ inline void td_row_f32(const DevBeam& bm, int64_t c, const Segment& s
             // of the mean, so value bins over mean -+ 1.0625 sd hold it; the
             // radix select is the fallback for rows the bins do not settle.
             constexpr int NB = NW * 128, CAP = NW * 128;   // both halves of s_hist
-            double sx = 0.0, sxx = 0.0;   // padding is +0 until the row is written
+            const uint32_t rank = (n - 1) / 2;
+            if (j == 0 && !tiny) {
+                // mean and deviation from the step's exact window sums (one thread)
+                if (tid == 0) {
+                    double S = 0.0, Q = 0.0;
+                    for (int w = 0; w < NW; w++) {
+                        S += (double)s_S[w];
+                        Q += u128_to_double(((u128)s_Q[w][1] << 64) | s_Q[w][0]);
+                    }
+                    const double m = S / n;
+                    s_mom[0][0] = ldexp(m, e);
+                    s_mom[0][1] = ldexp(sqrt(fmax(Q / n - m * m, 0.0)), e);
+                }
+            } else {
+                double sx = 0.0, sxx = 0.0;   // padding is +0 until the row is written
 #pragma unroll
-            for (int i = 0; i < VPT; i++) {
-                const double x = (double)get(i);
-                sx += x;
-                sxx += x * x;
-            }
+                for (int i = 0; i < VPT; i++) {
+                    const double x = (double)get(i);
+                    sx += x;
+                    sxx += x * x;
+                }
 #pragma unroll
-            for (int o = 1; o < 64; o <<= 1) {
-                sx += __shfl_xor(sx, o, 64);
-                sxx += __shfl_xor(sxx, o, 64);
-            }
-            if (lane == 0) {
-                s_mom[wave][0] = sx;
-                s_mom[wave][1] = sxx;
+                for (int o = 1; o < 64; o <<= 1) {
+                    sx += __shfl_xor(sx, o, 64);
+                    sxx += __shfl_xor(sxx, o, 64);
+                }
+                if (lane == 0) {
+                    s_mom[wave][0] = sx;
+                    s_mom[wave][1] = sxx;
+                }
+                __syncthreads();
+                if (tid == 0) {
+                    sx = sxx = 0.0;
+                    for (int w = 0; w < NW; w++) {
+                        sx += s_mom[w][0];
+                        sxx += s_mom[w][1];
+                    }
+                    const double m = sx / n;
+                    s_mom[0][0] = m;
+                    s_mom[0][1] = sqrt(fmax(sxx / n - m * m, 0.0));
+                }
             }
             for (int i = tid; i < NB; i += NT) s_hist[i] = 0;
             if (tid < 8) s_msel[tid] = 0;
             __syncthreads();
-            sx = sxx = 0.0;
-            for (int w = 0; w < NW; w++) {
-                sx += s_mom[w][0];
-                sxx += s_mom[w][1];
-            }
-            const double mu = sx / n, sd = sqrt(fmax(sxx / n - mu * mu, 0.0));
+            const double mu = s_mom[0][0], sd = s_mom[0][1];
+            uint32_t key = 0;
+            bool ok = false;
             const double rad = 1.0625 * sd + fabs(mu) * 0x1p-20;
             const float lo = (float)(mu - rad), hi = (float)(mu + rad);
             const float wdt = hi - lo;
-            uint32_t key = 0;
-            const bool ok = isfinite(lo) && isfinite(hi) && wdt >= 0x1p-100f && isfinite((float)NB / wdt) &&
-                            wg_select_bins<NT, NB, CAP>((n - 1) / 2, lo, hi, s_hist, s_hist + NB, s_tot, s_msel,
-                                                        [&](auto&& add) {
-                                                            if (full) {
+            if (!ok)
+                ok = isfinite(lo) && isfinite(hi) && wdt >= 0x1p-100f && isfinite((float)NB / wdt) &&
+                     wg_select_bins<NT, NB, CAP>(rank, lo, hi, s_hist, s_hist + NB, s_tot, s_msel,
+                                                 [&](auto&& add) {
+                                                     if (full) {
 #pragma unroll
-                                                                for (int i = 0; i < VPT; i++) add(get(i));
-                                                            } else {
+                                                         for (int i = 0; i < VPT; i++) add(get(i));
+                                                     } else {
 #pragma unroll
-                                                                for (int i = 0; i < VPT; i++)
-                                                                    if (i < nv) add(get(i));
-                                                            }
-                                                        }, &key);
+                                                         for (int i = 0; i < VPT; i++)
+                                                             if (i < nv) add(get(i));
+                                                     }
+                                                 }, &key);
             if (!ok)
                 key = wg_select_key<NT>((uint64_t)(n - 1) / 2, s_hist, s_tot, s_sel, [&](auto&& add) {
                     if (full) {
