@@ -357,22 +357,25 @@ __device__ inline void td_row_f32(const DevBeam& bm, int64_t c, const Segment& s
     // rank floor((n-1)/2)); known_med says m is current.
     bool known_med = false;
     float cur_med = 0.0f;
-    // First window: after the first step the exact sums change only by the
-    // replaced samples, so each lane accumulates (r - x) and (r^2 - x^2) of the
-    // samples it replaces (integers in units of the window) and the next step
-    // adds those deltas to the running totals wave 0 keeps.
-    int64_t dS = 0;
-    u128 dQ = 0;          // two's complement: the deltas may be negative
-    i128 St_run = 0;      // wave 0: running exact sums of the first window
-    u128 Qt_run = 0;
+    // After the first step the exact sums change only by the replaced
+    // samples, so each lane accumulates (r - x) and (r^2 - x^2) of the samples
+    // it replaces (integers in units of each window, a value and its
+    // replacement each in the window that holds it) and the next step adds
+    // those deltas to the running totals wave 0 keeps.
+    int64_t dS = 0, dS1 = 0;
+    u128 dQ = 0, dQ1 = 0;           // two's complement: the deltas may be negative
+    i128 St_run = 0, St1_run = 0;   // wave 0: running exact sums of both windows
+    u128 Qt_run = 0, Qt1_run = 0;
     for (int j = 0; j < seg.n_td && !bad && !to_two; j++) {
         const SegStep& st = seg.td[j];
         // exact window sums (both windows when the row has values below the first)
         int64_t S = 0, S1 = 0;
         u128 Q = 0, Q1 = 0;
-        if (!tiny && j > 0) {
+        if (j > 0) {
             S = dS;
             Q = dQ;
+            S1 = dS1;
+            Q1 = dQ1;
         } else if (!tiny) {
 #pragma unroll
             for (int i0 = 0; i0 < VPT; i0 += 32) {
@@ -383,7 +386,7 @@ __device__ inline void td_row_f32(const DevBeam& bm, int64_t c, const Segment& s
                 Q += winacc_q(w);
             }
         } else {
-#pragma unroll 1
+#pragma unroll
             for (int i0 = 0; i0 < VPT; i0 += 32) {
                 WinAcc w{0.0, 0.0, 0.0}, w1{0.0, 0.0, 0.0};
 #pragma unroll
@@ -398,6 +401,8 @@ __device__ inline void td_row_f32(const DevBeam& bm, int64_t c, const Segment& s
                 S1 += (int64_t)w1.s;
                 Q1 += winacc_q(w1);
             }
+        }
+        if (tiny) {
             S1 = wave_add_i64(S1);
             Q1 = group_add_u128(Q1, 64);
         }
@@ -506,14 +511,16 @@ __device__ inline void td_row_f32(const DevBeam& bm, int64_t c, const Segment& s
                 St1 += s_S1[w];
                 Qt1 += ((u128)s_Q1[w][1] << 64) | s_Q1[w][0];
             }
-            if (!TWO) {   // step j > 0: St, Qt are the deltas of step j - 1's replacements
-                if (j > 0) {
-                    St += St_run;
-                    Qt += Qt_run;
-                }
-                St_run = St;
-                Qt_run = Qt;
+            if (j > 0) {   // the sums of step j > 0 are the deltas of step j - 1's replacements
+                St += St_run;
+                Qt += Qt_run;
+                St1 += St1_run;
+                Qt1 += Qt1_run;
             }
+            St_run = St;
+            Qt_run = Qt;
+            St1_run = St1;
+            Qt1_run = Qt1;
             float H, Lo, rm;
             if (!TWO) {
                 const u128 Sa = St < 0 ? (u128)(-St) : (u128)St;
@@ -567,9 +574,15 @@ __device__ inline void td_row_f32(const DevBeam& bm, int64_t c, const Segment& s
         known_med = st.replace == RFIM_REPLACE_MEDIAN && !(med < Lo) && !(med > H);
         cur_med = med;
         uint32_t cnt = 0;
-        const int64_t ra = (int64_t)((double)r * sc);   // r lies in the first window (else the row left it)
+        // r lies in the first window (else the row left this kernel), or with
+        // two windows in either
+        const bool rlo = tiny && below_window(__float_as_uint(r), thr);
+        const int64_t ra = rlo ? 0 : (int64_t)((double)r * sc);
+        const int64_t ra1 = rlo ? (int64_t)((double)r * sc2) : 0;
         dS = 0;
         dQ = 0;
+        dS1 = 0;
+        dQ1 = 0;
         auto apply_one = [&](int i) {
             const float x = get(i);
             const bool f = x < Lo || x > H;
@@ -579,6 +592,14 @@ __device__ inline void td_row_f32(const DevBeam& bm, int64_t c, const Segment& s
                     const int64_t a = (int64_t)((double)x * sc);
                     dS += ra - a;
                     dQ += (u128)((i128)ra * ra) - (u128)((i128)a * a);
+                } else {
+                    const bool xlo = below_window(__float_as_uint(x), thr);
+                    const int64_t a = xlo ? 0 : (int64_t)((double)x * sc);
+                    const int64_t a1 = xlo ? (int64_t)((double)x * sc2) : 0;
+                    dS += ra - a;
+                    dQ += (u128)((i128)ra * ra) - (u128)((i128)a * a);
+                    dS1 += ra1 - a1;
+                    dQ1 += (u128)((i128)ra1 * ra1) - (u128)((i128)a1 * a1);
                 }
             }
             cnt += f ? 1u : 0u;
