@@ -1174,9 +1174,9 @@ __global__ __launch_bounds__(kF32Block) void k_fused_f32(const DevBeam* __restri
     }
     __syncthreads();
 
-    // ---- phase 3: tile back to rows (four items per thread per pass: their
+    // ---- phase 3: tile back to rows (sixteen items per thread per pass: their
     // LDS reads are issued together)
-#pragma unroll 4
+#pragma unroll 16
     for (int it = tid; it < nitems; it += kF32Block) {
         const int c = it >> tq_log;
         const int q = it & (TQ - 1);
