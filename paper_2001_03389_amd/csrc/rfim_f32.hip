@@ -1048,6 +1048,9 @@ __global__ __launch_bounds__(kF32Block) void k_fused_f32(const DevBeam* __restri
         float2 fr[kB1];
         int cs[kB1], qs[kB1];
         bool oks[kB1];
+        // the batch's loads go out at raised wave priority (the other
+        // work-group on the CU is then usually in its FD phase)
+        __builtin_amdgcn_s_setprio(2);
 #pragma unroll
         for (int u = 0; u < kB1; u++) {
             const int it = it0 + u * kF32Block;
@@ -1072,6 +1075,7 @@ __global__ __launch_bounds__(kF32Block) void k_fused_f32(const DevBeam* __restri
             }
             if (k.n_td > 0) fr[u] = k.fast[c];
         }
+        __builtin_amdgcn_s_setprio(0);
 #pragma unroll
         for (int u = 0; u < kB1; u++) {
             if (!oks[u]) continue;
