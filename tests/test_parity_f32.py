@@ -191,7 +191,8 @@ def median_rows(T, rng):
     """Rows whose lower medians the value-bin select settles, or hands to the
     radix select: Gaussian, skewed, bimodal (the median between the modes),
     integers with ties far beyond a bin's capacity at the median, a majority
-    of signed zeros, one huge spike, bandpass-like integer levels."""
+    of signed zeros, one huge spike, bandpass-like integer levels, all zeros
+    and a constant row."""
     rows = [rng.standard_normal(T),
             rng.exponential(1.0, T),
             np.where(rng.random(T) < 0.5, -5.0, 5.0) + rng.standard_normal(T) * 0.1,
@@ -199,7 +200,9 @@ def median_rows(T, rng):
             np.where(rng.random(T) < 0.5, -0.0, 0.0) + (rng.random(T) < 0.2) * rng.standard_normal(T),
             np.r_[rng.standard_normal(T - 1), 3.0e37],
             np.clip(np.round(rng.normal(80, 8, T)), 0, 255),
-            rng.standard_normal(T) * 1e-3 + 7.0]
+            rng.standard_normal(T) * 1e-3 + 7.0,
+            np.zeros(T),                       # a range of width zero
+            np.full(T, 3.5)]                   # one bin holding every value
     return np.stack(rows).astype(np.float32)
 
 
