@@ -34,20 +34,59 @@ __device__ inline uint32_t wave_max_u32(uint32_t v) {
     for (int o = 32; o >= 1; o >>= 1) v = max(v, (uint32_t)__shfl_xor((int)v, o, 64));
     return v;
 }
+// The value of this lane's partner at distance o (1, 2, 4, ... 32) in a
+// whole-wave reduction whose levels go in ascending order: DPP within 16-lane
+// rows (quad swaps, then the half-row and row mirrors, whose partners lie in
+// the other half once each half holds one value), LDS permutes across rows.
+template <int O>
+__device__ inline uint32_t lane_partner(uint32_t v) {
+    if constexpr (O == 1) return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xf, 0xf, false);
+    else if constexpr (O == 2) return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xf, 0xf, false);
+    else if constexpr (O == 4) return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x141, 0xf, 0xf, false);
+    else if constexpr (O == 8) return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x140, 0xf, 0xf, false);
+    else return (uint32_t)__shfl_xor((int)v, O, 64);
+}
+template <int O>
+__device__ inline uint64_t lane_partner64(uint64_t v) {
+    return (uint64_t)lane_partner<O>((uint32_t)v) | ((uint64_t)lane_partner<O>((uint32_t)(v >> 32)) << 32);
+}
 __device__ inline uint32_t wave_min_u32(uint32_t v) {
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) v = min(v, (uint32_t)__shfl_xor((int)v, o, 64));
-    return v;
+    v = min(v, lane_partner<1>(v));
+    v = min(v, lane_partner<2>(v));
+    v = min(v, lane_partner<4>(v));
+    v = min(v, lane_partner<8>(v));
+    v = min(v, lane_partner<16>(v));
+    return min(v, lane_partner<32>(v));
 }
 __device__ inline uint32_t wave_add_u32(uint32_t v) {
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) v += (uint32_t)__shfl_xor((int)v, o, 64);
-    return v;
+    v += lane_partner<1>(v);
+    v += lane_partner<2>(v);
+    v += lane_partner<4>(v);
+    v += lane_partner<8>(v);
+    v += lane_partner<16>(v);
+    return v + lane_partner<32>(v);
 }
 __device__ inline int64_t wave_add_i64(int64_t v) {
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
+    uint64_t u = (uint64_t)v;
+    u += lane_partner64<1>(u);
+    u += lane_partner64<2>(u);
+    u += lane_partner64<4>(u);
+    u += lane_partner64<8>(u);
+    u += lane_partner64<16>(u);
+    return (int64_t)(u + lane_partner64<32>(u));
+}
+template <int O>
+__device__ inline u128 u128_partner(u128 v) {
+    return (u128)lane_partner64<O>((uint64_t)v) | ((u128)lane_partner64<O>((uint64_t)(v >> 64)) << 64);
+}
+// sum of u128 over the whole wave
+__device__ inline u128 wave_add_u128(u128 v) {
+    v += u128_partner<1>(v);
+    v += u128_partner<2>(v);
+    v += u128_partner<4>(v);
+    v += u128_partner<8>(v);
+    v += u128_partner<16>(v);
+    return v + u128_partner<32>(v);
 }
 // sum of u128 over lanes xor-partnered within groups of G (power of two)
 __device__ inline u128 group_add_u128(u128 v, int G) {
@@ -404,10 +443,10 @@ __device__ inline void td_row_f32(const DevBeam& bm, int64_t c, const Segment& s
         }
         if (tiny) {
             S1 = wave_add_i64(S1);
-            Q1 = group_add_u128(Q1, 64);
+            Q1 = wave_add_u128(Q1);
         }
         S = wave_add_i64(S);
-        Q = group_add_u128(Q, 64);
+        Q = wave_add_u128(Q);
         if (lane == 0) {
             s_S[wave] = S;
             s_Q[wave][0] = (uint64_t)Q;
