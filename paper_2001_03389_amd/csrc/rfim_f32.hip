@@ -79,6 +79,22 @@ template <int O>
 __device__ inline u128 u128_partner(u128 v) {
     return (u128)lane_partner64<O>((uint64_t)v) | ((u128)lane_partner64<O>((uint64_t)(v >> 64)) << 64);
 }
+__device__ inline uint32_t wave_max_dpp(uint32_t v) {
+    v = max(v, lane_partner<1>(v));
+    v = max(v, lane_partner<2>(v));
+    v = max(v, lane_partner<4>(v));
+    v = max(v, lane_partner<8>(v));
+    v = max(v, lane_partner<16>(v));
+    return max(v, lane_partner<32>(v));
+}
+__device__ inline uint32_t wave_or_dpp(uint32_t v) {
+    v |= lane_partner<1>(v);
+    v |= lane_partner<2>(v);
+    v |= lane_partner<4>(v);
+    v |= lane_partner<8>(v);
+    v |= lane_partner<16>(v);
+    return v | lane_partner<32>(v);
+}
 // sum of u128 over the whole wave
 __device__ inline u128 wave_add_u128(u128 v) {
     v += u128_partner<1>(v);
@@ -760,7 +776,7 @@ __device__ inline U512 group_add_u256(U512 v, int G) {
 // statistics in both windows.  Returns 0 when done, 1 when the time sample
 // needs the wide path (values below the last window), 2 (TWO = false only)
 // when it needs the two-window kernel; x is then not final.
-template <int B, int BPL, bool TWO>
+template <int B, int BPL, bool TWO, bool WAVE = false>
 __device__ inline int fd_column_f32(float (&x)[BPL][B], uint32_t (&fw)[BPL][B / 4], const bool (&act)[BPL], int G2,
                                     uint32_t C, const Segment& seg, uint64_t lc[4]) {
     uint32_t emax = 0, tmin = 0xFFFFFFFFu;
@@ -772,8 +788,13 @@ __device__ inline int fd_column_f32(float (&x)[BPL][B], uint32_t (&fw)[BPL][B / 
             emax = max(emax, bb);
             tmin = min(tmin, bb - 1u);
         }
-    emax = group_max_u32(emax, G2);
-    tmin = group_min_u32(tmin, G2);
+    if constexpr (WAVE) {   // one time sample per wave (G2 == 64)
+        emax = wave_max_dpp(emax);
+        tmin = wave_min_u32(tmin);
+    } else {
+        emax = group_max_u32(emax, G2);
+        tmin = group_min_u32(tmin, G2);
+    }
     const int EM = f32_E(emax);
     const uint32_t thr = window_thr(EM), thr2 = window_thr2(EM);
     if (tmin != 0xFFFFFFFFu && tmin + 1u < thr2) return 1;
@@ -816,7 +837,8 @@ __device__ inline int fd_column_f32(float (&x)[BPL][B], uint32_t (&fw)[BPL][B / 
                 const u128 Sa = Sb < 0 ? (u128)(-(i128)Sb) : (u128)Sb;
                 if (act[kk]) V += (u128)B * Qb - Sa * Sa;
             }
-            V = group_add_u128(V, G2);
+            if constexpr (WAVE) V = wave_add_u128(V);
+            else V = group_add_u128(V, G2);
             // sum over the time sample of Z_c^2 = B * sum_b (B*Q_b - S_b^2);
             // the integer radius z is only needed where the FP64 cut is not
             // certified (below)
@@ -911,7 +933,8 @@ __device__ inline int fd_column_f32(float (&x)[BPL][B], uint32_t (&fw)[BPL][B / 
             }
             lc[s >> 2] += (uint64_t)__popcll(fm) << (16 * (s & 3));
         }
-        bad = group_or_u32(bad, G2);
+        if constexpr (WAVE) bad = wave_or_dpp(bad);
+        else bad = group_or_u32(bad, G2);
         if (bad) return (bad & 1u) ? 1 : 2;
     }
     return 0;
@@ -954,7 +977,8 @@ __device__ void fd_fast_f32(const F32Tile& k, const Segment& seg, float* tile, u
             for (int j = 0; j < B / 4; j++) fw[kk][j] = 0;
         }
         uint64_t lc[4];
-        const int res = fd_column_f32<B, BPL, false>(x, fw, act, G2, C, seg, lc);
+        // two bins per lane means more than 64 bins: one time sample per wave
+        const int res = fd_column_f32<B, BPL, false, BPL == 2>(x, fw, act, G2, C, seg, lc);
         if (!colok) continue;
         if (res) {
             // the tile keeps this time sample's post-TD values for the other kernel
