@@ -70,7 +70,7 @@ def make_steps(steps):
     arr = (_Step * max(1, len(steps)))()
     for i, s in enumerate(steps):
         dom, k, rep, b = _step_tuple(s)
-        arr[i].domain = {"td": 0, "fd": 1}[dom]
+        arr[i].domain = {"td": 0, "fd": 1, "td_masked": 2}[dom]
         arr[i].replace = {"mean": 0, "median": 1}[rep]
         arr[i].k = float(k)
         arr[i].bin_size = int(b) if dom == "fd" else 0

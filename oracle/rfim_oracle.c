@@ -23,6 +23,11 @@
  *     bin's lower median).  Here the test is run on Z_c = B*y_c = B*x_c - S_b,
  *     which is the same test (scaling by B cancels on both sides).
  *
+ *   Masked TD step (a reading of the iterated cut, Sections IV and V-A): the
+ *     same test, but a run of consecutive masked TD steps keeps a per-sample
+ *     mask of what it has replaced, and each step's statistics, cut and
+ *     replacement value use only the unmasked samples of the row.
+ *
  *   Replacement (Section IV, strategy parameter): "mean" = the statistics'
  *     mean rounded to nearest, ties to even (uint8: to an integer, float32:
  *     to the nearest float32); "median" = element of rank floor((n-1)/2) in
@@ -466,11 +471,12 @@ static void sigma_test(const bi* v, int64_t n, const kexact* kx, uint8_t* flagge
 /* ------------------------------------------------------------------------ */
 #define OR_TD 0
 #define OR_FD 1
+#define OR_TD_MASKED 2
 #define OR_MEAN 0
 #define OR_MEDIAN 1
 
 typedef struct {
-    int32_t domain;  /* OR_TD / OR_FD */
+    int32_t domain;  /* OR_TD / OR_FD / OR_TD_MASKED */
     int32_t replace; /* OR_MEAN / OR_MEDIAN */
     double k;
     int64_t bin_size; /* FD: channels per bin; 0 = all channels */
@@ -508,6 +514,58 @@ int oracle_td_step(int dtype, void* data, int64_t C, int64_t T, int64_t stride, 
         }
     }
     free(v);
+    free(fl);
+    return 0;
+}
+
+/* One masked TD step on one beam, in place (a reading of the iterated TD
+ * cut of Sections IV and V-A in which a sample that was cut is set aside):
+ * mask is [C][T], 1 where an earlier step of the same run of masked TD steps
+ * replaced the sample.  Per row, the statistics, the cut and the replacement
+ * value (mean of the unmasked samples rounded to the data type, or their lower
+ * median) use only the m unmasked samples; the cut samples are replaced, get
+ * flag bit `bit` and join the mask.  A row with no unmasked sample is left as
+ * it is. */
+int oracle_td_step_masked(int dtype, void* data, int64_t C, int64_t T, int64_t stride, double k,
+                          int replace, uint8_t* flags, int bit, uint8_t* mask) {
+    if (C < 1 || T < 1 || stride < T || !valid_k(k) || T >= ((int64_t)1 << 32) || !mask) return -1;
+    kexact kx;
+    k_split(&kx, k);
+    size_t es = dtype == DT_U8 ? 1 : 4;
+    bi* v = (bi*)malloc(sizeof(bi) * (size_t)T);
+    int64_t* idx = (int64_t*)malloc(sizeof(int64_t) * (size_t)T);
+    unsigned char* kept = (unsigned char*)malloc((size_t)T * es);
+    uint8_t* fl = (uint8_t*)malloc((size_t)T);
+    unsigned char rbuf[4];
+    if (!v || !idx || !kept || !fl) abort();
+    for (int64_t c = 0; c < C; c++) {
+        int64_t base = c * stride, m = 0;
+        for (int64_t t = 0; t < T; t++) {
+#if ORACLE_MUTANT != 9 /* planted: set-aside samples stay in the statistics */
+            if (mask[c * T + t]) continue;
+#endif
+            idx[m] = t;
+            value_int(&v[m], dtype, data, base + t);
+            copy_elem(dtype, kept, m, data, base + t);
+            m++;
+        }
+        if (m == 0) continue;
+        bi S1;
+        sigma_test(v, m, &kx, fl, &S1);
+        if (replace == OR_MEAN)
+            store_rounded(dtype, rbuf, 0, &S1, (uint32_t)m);
+        else
+            lower_median(dtype, kept, 0, 1, m, rbuf, 0);
+        for (int64_t i = 0; i < m; i++) {
+            if (!fl[i]) continue;
+            copy_elem(dtype, data, base + idx[i], rbuf, 0);
+            mask[c * T + idx[i]] = 1;
+            if (flags) flags[base + idx[i]] |= (uint8_t)(1u << bit);
+        }
+    }
+    free(v);
+    free(idx);
+    free(kept);
     free(fl);
     return 0;
 }
@@ -582,25 +640,42 @@ int oracle_pipeline(int dtype, const void* in, void* out, int64_t C, int64_t T, 
         if (steps[s].domain == OR_FD) {
             int64_t B = steps[s].bin_size == 0 ? C : steps[s].bin_size;
             if (B < 1 || C % B != 0) return -1;
-        } else if (steps[s].domain != OR_TD) {
+        } else if (steps[s].domain != OR_TD && steps[s].domain != OR_TD_MASKED) {
             return -1;
         }
     }
+    /* the mask of a run of consecutive masked TD steps (cleared when a run starts) */
+    uint8_t* mask = NULL;
+    for (int s = 0; s < nsteps; s++)
+        if (steps[s].domain == OR_TD_MASKED && !mask) {
+            mask = (uint8_t*)malloc((size_t)(C * T));
+            if (!mask) abort();
+        }
     if (in != out)
         for (int64_t c = 0; c < C; c++)
             memcpy((unsigned char*)out + c * stride * es, (const unsigned char*)in + c * stride * es,
                    (size_t)T * es);
     if (flags)
         for (int64_t c = 0; c < C; c++) memset(flags + c * stride, 0, (size_t)T);
-    for (int s = 0; s < nsteps; s++) {
+    int rc = 0;
+    for (int s = 0; s < nsteps && !rc; s++) {
         const or_step* st = &steps[s];
-        int rc = st->domain == OR_TD
-                     ? oracle_td_step(dtype, out, C, T, stride, st->k, st->replace, flags, s)
-                     : oracle_fd_step(dtype, out, C, T, stride, st->k, st->bin_size, st->replace,
-                                      flags, s);
-        if (rc) return rc;
+        if (st->domain == OR_TD_MASKED) {
+#if ORACLE_MUTANT == 10 /* planted: the mask is cleared only once, not at every run */
+            if (s == 0 || (steps[s - 1].domain != OR_TD_MASKED && 0))
+#else
+            if (s == 0 || steps[s - 1].domain != OR_TD_MASKED)
+#endif
+                memset(mask, 0, (size_t)(C * T));
+            rc = oracle_td_step_masked(dtype, out, C, T, stride, st->k, st->replace, flags, s, mask);
+        } else if (st->domain == OR_TD) {
+            rc = oracle_td_step(dtype, out, C, T, stride, st->k, st->replace, flags, s);
+        } else {
+            rc = oracle_fd_step(dtype, out, C, T, stride, st->k, st->bin_size, st->replace, flags, s);
+        }
     }
-    return 0;
+    free(mask);
+    return rc;
 }
 
 /* Helpers exposed for the pins. */

@@ -76,6 +76,27 @@ def td_step(x: np.ndarray, k, replace="mean"):
     return out, flags
 
 
+def td_step_masked(x: np.ndarray, k, replace, mask):
+    """Masked TD step: per row, only the samples with mask False take part;
+    the cut ones are replaced and join the mask (mask is updated in place)."""
+    out = x.copy()
+    flags = np.zeros(x.shape, dtype=bool)
+    for c in range(x.shape[0]):
+        idx = [t for t in range(x.shape[1]) if not mask[c, t]]
+        if not idx:
+            continue
+        row = x[c, idx]
+        vals = [Fraction(int(v)) if x.dtype == np.uint8 else f32_exact(v) for v in row]
+        fl, mu = outliers(vals, k)
+        r = round_dtype(mu, x.dtype) if replace == "mean" else lower_median(row, x.dtype)
+        for t, f in zip(idx, fl):
+            if f:
+                out[c, t] = r
+                flags[c, t] = True
+                mask[c, t] = True
+    return out, flags
+
+
 def fd_step(x: np.ndarray, k, bin_size=32, replace="mean"):
     C, T = x.shape
     B = C if bin_size == 0 else bin_size
@@ -100,8 +121,13 @@ def pipeline(x: np.ndarray, steps):
     """steps: iterable of (domain, k, replace, bin_size).  Returns (out, flagbits)."""
     cur = x.copy()
     bits = np.zeros(x.shape, dtype=np.uint8)
+    mask = None
     for j, (dom, k, rep, b) in enumerate(steps):
-        if dom == "td":
+        if dom == "td_masked":
+            if j == 0 or steps[j - 1][0] != "td_masked":
+                mask = np.zeros(x.shape, dtype=bool)   # a new run of masked steps
+            cur, fl = td_step_masked(cur, k, rep, mask)
+        elif dom == "td":
             cur, fl = td_step(cur, k, rep)
         else:
             cur, fl = fd_step(cur, k, b, rep)

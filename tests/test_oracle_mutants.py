@@ -13,7 +13,8 @@ import bruteforce as bf
 
 MUTANTS = {1: "'>=' instead of '>'", 2: "sample std", 3: "ties round up", 4: "upper median",
            5: "wrong bin mean", 6: "raw-column statistics in FD", 7: "wrong bin replaced",
-           8: "last sample skipped"}
+           8: "last sample skipped", 9: "set-aside samples in masked statistics",
+           10: "mask not cleared at a new run of masked steps"}
 
 
 def _agrees_with_bruteforce(lib) -> bool:
@@ -26,6 +27,15 @@ def _agrees_with_bruteforce(lib) -> bool:
         want, wbits = bf.pipeline(x, steps)
         got, gbits = oracle.pipeline(x, steps, want_flags=True, _lib_override=lib)
         if not (np.array_equal(got.view(np.uint8), want.view(np.uint8)) and np.array_equal(gbits, wbits)):
+            return False
+    for seed in range(40):
+        rng = np.random.default_rng(8000 + seed)
+        C, T = int(rng.integers(1, 6)), int(rng.integers(2, 13))
+        x = rng.integers(0, int(rng.choice([2, 8, 256])), size=(C, T)).astype(np.uint8)
+        steps = pins.rand_steps(rng, C, int(rng.integers(2, 6)), masked=True)
+        want, wbits = bf.pipeline(x, steps)
+        got, gbits = oracle.pipeline(x, steps, want_flags=True, _lib_override=lib)
+        if not (np.array_equal(got, want) and np.array_equal(gbits, wbits)):
             return False
     # hand cases and closed forms: row [0 x9, 25] has mean 2.5 and the 25 sits
     # exactly 3 sigma out, so at k = 2.75 it is replaced by round(2.5) = 2

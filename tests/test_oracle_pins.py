@@ -24,11 +24,13 @@ import oracle
 KS = [0.0, 0.5, 1.0, 1.25, 1.5, 2.0, 2.75, 3.0, 3.25, 4.0]
 
 
-def rand_steps(rng, C, nsteps):
+def rand_steps(rng, C, nsteps, masked=False):
     divs = [b for b in range(1, C + 1) if C % b == 0]
     out = []
     for _ in range(nsteps):
         dom = "td" if rng.random() < 0.5 else "fd"
+        if masked and dom == "td" and rng.random() < 0.7:
+            dom = "td_masked"
         k = float(rng.choice(KS)) if rng.random() < 0.7 else float(rng.uniform(0.0, 3.0))
         rep = "mean" if rng.random() < 0.5 else "median"
         b = int(rng.choice(divs)) if dom == "fd" else 0
@@ -76,6 +78,68 @@ def test_bruteforce_f32_random(seed):
     got, gbits = oracle.pipeline(x, steps, want_flags=True)
     np.testing.assert_array_equal(got.view(np.uint32), want.view(np.uint32))
     np.testing.assert_array_equal(gbits, wbits)
+
+
+@pytest.mark.parametrize("seed", range(40))
+def test_bruteforce_masked_u8_random(seed):
+    """Masked TD steps (mixed with TD and FD steps) against the brute force."""
+    rng = np.random.default_rng(7000 + seed)
+    C = int(rng.integers(1, 7))
+    T = int(rng.integers(1, 14))
+    hi = int(rng.choice([2, 8, 256]))
+    x = rng.integers(0, hi, size=(C, T)).astype(np.uint8)
+    steps = rand_steps(rng, C, int(rng.integers(1, 6)), masked=True)
+    want, wbits = bf.pipeline(x, steps)
+    got, gbits = oracle.pipeline(x, steps, want_flags=True)
+    np.testing.assert_array_equal(got, want)
+    np.testing.assert_array_equal(gbits, wbits)
+
+
+@pytest.mark.parametrize("seed", range(16))
+def test_bruteforce_masked_f32_random(seed):
+    rng = np.random.default_rng(7500 + seed)
+    C = int(rng.integers(1, 6))
+    T = int(rng.integers(1, 11))
+    x = rand_f32(rng, (C, T))
+    steps = rand_steps(rng, C, int(rng.integers(1, 5)), masked=True)
+    want, wbits = bf.pipeline(x, steps)
+    got, gbits = oracle.pipeline(x, steps, want_flags=True)
+    np.testing.assert_array_equal(got.view(np.uint32), want.view(np.uint32))
+    np.testing.assert_array_equal(gbits, wbits)
+
+
+def test_first_masked_step_is_a_td_step():
+    """A run's first masked step sees an empty mask: it is the plain TD step."""
+    rng = np.random.default_rng(7900)
+    x = rng.integers(0, 256, size=(12, 700)).astype(np.uint8)
+    x[:, ::37] = 255
+    for k, rep in ((2.5, "mean"), (1.0, "median"), (0.0, "mean")):
+        a, fa = oracle.pipeline(x, [("td_masked", k, rep, 0)], want_flags=True)
+        b, fb = oracle.pipeline(x, [("td", k, rep, 0)], want_flags=True)
+        np.testing.assert_array_equal(a, b)
+        np.testing.assert_array_equal(fa, fb)
+
+
+def test_masked_run_cuts_each_sample_once():
+    """Within a run of masked steps a sample is cut at most once, keeps the
+    value of the step that cut it, and every sample not cut is unchanged; the
+    number of set-aside samples never falls."""
+    rng = np.random.default_rng(7901)
+    x = np.clip(rng.normal(100, 12, size=(16, 900)), 0, 255).astype(np.uint8)
+    x[rng.random(x.shape) < 0.03] = 250
+    steps = [("td_masked", 2.0, "mean", 0)] * 5
+    out, fl = oracle.pipeline(x, steps, want_flags=True)
+    bits = np.unpackbits(fl[..., None], axis=-1).sum(axis=-1)
+    assert bits.max() == 1 and bits.sum() > 0
+    untouched = fl == 0
+    np.testing.assert_array_equal(out[untouched], x[untouched])
+    counts = [int(((fl >> j) & 1).sum()) for j in range(5)]
+    assert counts[0] > 0 and all(c >= 0 for c in counts)
+    for c in range(x.shape[0]):
+        for j in range(5):
+            cut = ((fl[c] >> j) & 1).astype(bool)
+            if cut.any():   # one replacement value per row and step
+                assert len(set(out[c][cut].tolist())) == 1
 
 
 def test_exhaustive_small_rows():
