@@ -64,7 +64,15 @@ typedef enum {
 
 typedef enum { RFIM_U8 = 0, RFIM_F32 = 1 } rfim_dtype;
 typedef enum { RFIM_REPLACE_MEAN = 0, RFIM_REPLACE_MEDIAN = 1 } rfim_replace;
-typedef enum { RFIM_TD = 0, RFIM_FD = 1 } rfim_domain;
+/* RFIM_TD_MASKED: a TD step whose statistics, cut and replacement value use
+ * only the samples of the row that no earlier step of the same run of
+ * consecutive RFIM_TD_MASKED steps replaced (a reading of the iterated TD cut
+ * of Sections IV and V-A in which a cut sample is set aside, not re-tested);
+ * the run's mask starts empty, so its first step is an RFIM_TD step, and a
+ * sample it cut keeps that step's replacement value and flag bit.  A row whose
+ * samples are all set aside is left as it is.  uint8 beams only: a call with
+ * a float32 beam returns RFIM_ERR_UNSUPPORTED. */
+typedef enum { RFIM_TD = 0, RFIM_FD = 1, RFIM_TD_MASKED = 2 } rfim_domain;
 
 /* One beam.  `in` and `out` are device pointers to [nchan][row_stride]
  * elements; out == in processes in place (the original data is then

@@ -22,7 +22,7 @@ RFIM_ERR_SCRATCH = -7
 RFIM_NOALLOC_SCRATCH_BYTES = 32 << 20
 RFIM_U8, RFIM_F32 = 0, 1
 RFIM_REPLACE_MEAN, RFIM_REPLACE_MEDIAN = 0, 1
-RFIM_TD, RFIM_FD = 0, 1
+RFIM_TD, RFIM_FD, RFIM_TD_MASKED = 0, 1, 2
 RFIM_KERNEL_TD_ROWS_U8, RFIM_KERNEL_FUSED_U8 = 0, 1
 RFIM_KERNEL_TD_ROWS_F32, RFIM_KERNEL_FUSED_F32, RFIM_KERNEL_TD_WIDE_F32, RFIM_KERNEL_FD_WIDE_F32 = 2, 3, 4, 5
 RFIM_KERNEL_TD_TWO_F32, RFIM_KERNEL_FD_TWO_F32 = 6, 7
@@ -200,7 +200,7 @@ def _step_fields(s):
         dom, k, rep, binsz = s.domain, s.k, s.replace, s.bin_size
     else:
         dom, k, rep, binsz = s
-    d = {"td": RFIM_TD, "fd": RFIM_FD}.get(dom, dom)
+    d = {"td": RFIM_TD, "fd": RFIM_FD, "td_masked": RFIM_TD_MASKED}.get(dom, dom)
     r = {"mean": RFIM_REPLACE_MEAN, "median": RFIM_REPLACE_MEDIAN}.get(rep, rep)
     return int(d), int(r), float(k), int(binsz) if int(d) == RFIM_FD else 0
 

@@ -89,14 +89,18 @@ size_t beam_span(const rfim_beam& b) {
     return (size_t)((b.nchan - 1) * b.row_stride + b.nsamp) * elem_size(b.dtype);
 }
 
-// The step list as runs of [consecutive TD steps][consecutive FD steps].
+// The step list as runs of [consecutive TD steps][consecutive FD steps]; the
+// TD steps of a run are all masked or all unmasked (a change starts a new run,
+// and with it a new mask).
 std::vector<Segment> segments_of(const rfim_step* steps, int32_t nsteps) {
     std::vector<Segment> out;
     int s = 0;
     while (s < nsteps) {
         Segment seg;
         std::memset(&seg, 0, sizeof(seg));
-        while (s < nsteps && steps[s].domain == RFIM_TD) {
+        if (steps[s].domain == RFIM_TD_MASKED) seg.td_masked = 1;
+        const int32_t td_kind = seg.td_masked ? RFIM_TD_MASKED : RFIM_TD;
+        while (s < nsteps && steps[s].domain == td_kind) {
             SegStep& d = seg.td[seg.n_td++];
             d.kx = make_k(steps[s].k);
             d.replace = steps[s].replace;
@@ -166,7 +170,8 @@ rfim_status validate(const rfim_beam* beams, int32_t nbeams, const rfim_step* st
     if (nsteps > 0 && !steps) return RFIM_ERR_INVALID_ARG;
     for (int s = 0; s < nsteps; s++) {
         const rfim_step& st = steps[s];
-        if (st.domain != RFIM_TD && st.domain != RFIM_FD) return RFIM_ERR_INVALID_ARG;
+        if (st.domain != RFIM_TD && st.domain != RFIM_FD && st.domain != RFIM_TD_MASKED)
+            return RFIM_ERR_INVALID_ARG;
         if (st.replace != RFIM_REPLACE_MEAN && st.replace != RFIM_REPLACE_MEDIAN)
             return RFIM_ERR_INVALID_ARG;
         if (!std::isfinite(st.k) || st.k < 0.0) return RFIM_ERR_INVALID_ARG;
@@ -194,6 +199,11 @@ rfim_status validate(const rfim_beam* beams, int32_t nbeams, const rfim_step* st
             if (B < 1 || b.nchan % B != 0) return RFIM_ERR_INVALID_ARG;
         }
     }
+    // masked TD steps run on the uint8 row histograms only
+    for (int s = 0; s < nsteps; s++)
+        if (steps[s].domain == RFIM_TD_MASKED)
+            for (int i = 0; i < nbeams; i++)
+                if (beams[i].dtype != RFIM_U8) return RFIM_ERR_UNSUPPORTED;
     return RFIM_OK;
 }
 

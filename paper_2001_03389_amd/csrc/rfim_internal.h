@@ -40,7 +40,7 @@ struct SegStep {
 struct Segment {
     int32_t n_td, n_fd;
     int32_t flags_mode;  // 0 = no flags, 1 = write fresh, 2 = OR into existing
-    int32_t pad;
+    int32_t td_masked;   // 1: the TD steps are one run of masked steps
     SegStep td[kMaxSteps];
     SegStep fd[kMaxSteps];
 };

@@ -70,7 +70,7 @@ std::string tune_key(const rfim_beam* shapes, int32_t nbeams, const rfim_step* s
     k += ";";
     for (int s = 0; s < nsteps; s++) {
         const rfim_step& st = steps[s];
-        std::snprintf(buf, sizeof buf, "%s%s:%.17g:%s:%lld", s ? "," : "", st.domain == RFIM_TD ? "td" : "fd", st.k,
+        std::snprintf(buf, sizeof buf, "%s%s:%.17g:%s:%lld", s ? "," : "", st.domain == RFIM_TD ? "td" : st.domain == RFIM_FD ? "fd" : "tdm", st.k,
                       st.replace == RFIM_REPLACE_MEDIAN ? "median" : "mean", (long long)st.bin_size);
         k += buf;
     }

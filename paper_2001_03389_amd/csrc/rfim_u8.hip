@@ -194,6 +194,15 @@ __device__ bool td_decide(const Segment& seg, uint64_t n, uint32_t hv[4], uint64
         }
         S1 = wave_sum_u64_split(S1) + S1J;   // below 2^39 / 2^47 for n < 2^31
         S2 = wave_sum_u64_split(S2) + S2J;
+        if (n == 0) {   // masked run: every sample of the row is set aside
+            if (lane == 0) {
+                s_lo[j] = 0;
+                s_hi[j] = 255;
+                s_r[j] = 0;
+                s_mv[j] = 0;
+            }
+            continue;
+        }
         int r;
         if (st.replace == RFIM_REPLACE_MEDIAN) {
             // lower median: the byte value holding rank floor((n-1)/2)
@@ -230,7 +239,9 @@ __device__ bool td_decide(const Segment& seg, uint64_t n, uint32_t hv[4], uint64
         const uint64_t moved = wave_sum_u32(moved32);   // at most n < 2^31
 #pragma unroll
         for (int u = 0; u < 4; u++) if (!((keepbits >> u) & 1)) hv[u] = 0;
-        if (nJ > 0 && r >= jlo && r <= jhi) {
+        if (seg.td_masked) {
+            n -= moved;   // the cut samples leave the statistics of the run
+        } else if (nJ > 0 && r >= jlo && r <= jhi) {
             nJ += moved;
             S1J += moved * (uint64_t)r;
             S2J += moved * (uint64_t)r * (uint64_t)r;
@@ -325,7 +336,7 @@ __device__ __attribute__((always_inline)) inline void td_row_group(const DevBeam
         //                             through step j iff L_j <= x <= H_j
         //   [23:16] value a sample first cut at step j ends with
         //   [31:24] flag bits it collects (step j and any later step that cuts
-        //           the replacement value)
+        //           the replacement value; step j alone in a masked run)
         if (lane < seg.n_td) {
             const int j = lane;
             int L = 0, H = 255;
@@ -335,7 +346,8 @@ __device__ __attribute__((always_inline)) inline void td_row_group(const DevBeam
             }
             int val = s_r[j];
             uint32_t f = seg.td[j].bit >= 0 ? (1u << seg.td[j].bit) : 0u;
-            for (int k = j + 1; k < seg.n_td; k++) {
+            // a masked run never tests a sample again once it is cut
+            for (int k = j + 1; k < seg.n_td && !seg.td_masked; k++) {
                 if (val < s_lo[k] || val > s_hi[k]) {
                     val = s_r[k];
                     if (seg.td[k].bit >= 0) f |= 1u << seg.td[k].bit;
