@@ -74,6 +74,24 @@ def test_bad_step_codes_rejected():
     assert rf.lib().rfim_pipeline_run(arr, 1, st, 1, None, None) == rf.RFIM_ERR_INVALID_ARG
 
 
+def test_masked_steps_refused_for_float32_on_host():
+    """Masked TD steps run on uint8 beams only; a call with any float32 beam is
+    refused before anything is enqueued."""
+    st = [("td_masked", 3.0, "mean", 0)]
+    assert _run([_beam(dtype=rf.RFIM_F32)], st) == rf.RFIM_ERR_UNSUPPORTED
+    assert _run([_beam(inp=1 << 20, out=1 << 21), _beam(dtype=rf.RFIM_F32)], st) == rf.RFIM_ERR_UNSUPPORTED
+    assert _run([_beam()], [("td_masked", -1.0, "mean", 0)]) == rf.RFIM_ERR_INVALID_ARG
+
+
+def test_header_step_codes_match_the_binding():
+    import os
+    import re
+    hdr = open(os.path.join(os.path.dirname(__file__), "..", "include", "rfim.h")).read()
+    m = re.search(r"typedef enum \{([^}]*)\} rfim_domain;", hdr)
+    vals = {k: int(v) for k, v in re.findall(r"(RFIM_\w+) = (\d+)", m.group(1))}
+    assert vals == {"RFIM_TD": rf.RFIM_TD, "RFIM_FD": rf.RFIM_FD, "RFIM_TD_MASKED": rf.RFIM_TD_MASKED}
+
+
 def test_plan_create_rejects_bad_shapes():
     arr = (rf.rfim_beam * 1)(_beam(nchan=6))
     st = rf.make_steps([("fd", 2.0, "mean", 4)])

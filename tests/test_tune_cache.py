@@ -49,7 +49,7 @@ def test_entry_without_schedule_reads_as_default(tmp_path):
     assert rf.tune_lookup(p, shapes_a(), STEPS) == (32, 81920, 64, 51200, 0, 4)
 
 
-@pytest.mark.parametrize("variant", ["flags", "stride", "k-ulp", "replace", "bin", "order"])
+@pytest.mark.parametrize("variant", ["flags", "stride", "k-ulp", "replace", "bin", "order", "masked"])
 def test_key_covers_shapes_and_steps(tmp_path, variant):
     p = str(tmp_path / "tune.json")
     rf.tune_store(p, shapes_a(), STEPS, (32, 81920, 64), 1.0)
@@ -64,6 +64,8 @@ def test_key_covers_shapes_and_steps(tmp_path, variant):
         st[1] = ("fd", 2.75, "median", 32)
     elif variant == "bin":
         st[1] = ("fd", 2.75, "mean", 64)
+    elif variant == "masked":
+        st[0] = ("td_masked",) + tuple(st[0][1:])
     else:
         sh = sh[::-1]
     assert rf.tune_lookup(p, sh, st) is None
