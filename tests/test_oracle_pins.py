@@ -120,6 +120,24 @@ def test_first_masked_step_is_a_td_step():
         np.testing.assert_array_equal(fa, fb)
 
 
+def test_masked_rows_with_every_sample_set_aside():
+    """k = 0 on rows of 0s and 2s with a non-integer mean cuts every sample at
+    the first masked step; later masked steps see no sample and change nothing
+    (brute force, and the state after the first step)."""
+    x = np.array([[0, 2, 2, 0, 2], [0, 2, 0, 2, 2], [1, 1, 1, 1, 1], [0, 2, 0, 2, 0]], np.uint8)
+    steps = [("td_masked", 0.0, "mean", 0), ("td_masked", 0.0, "median", 0), ("td_masked", 1.5, "mean", 0)]
+    want, wbits = bf.pipeline(x, steps)
+    got, gbits = oracle.pipeline(x, steps, want_flags=True)
+    np.testing.assert_array_equal(got, want)
+    np.testing.assert_array_equal(gbits, wbits)
+    first, fbits = oracle.pipeline(x, steps[:1], want_flags=True)
+    np.testing.assert_array_equal(got, first)
+    np.testing.assert_array_equal(gbits, fbits)
+    # rows 0, 1 and 3 have means 1.2 and 0.8: every sample cut and replaced by 1
+    assert (got[[0, 1, 3]] == 1).all() and (gbits[[0, 1, 3]] == 1).all()
+    assert (got[2] == 1).all() and (gbits[2] == 0).all()
+
+
 def test_masked_run_cuts_each_sample_once():
     """Within a run of masked steps a sample is cut at most once, keeps the
     value of the step that cut it, and every sample not cut is unchanged; the
